@@ -1,0 +1,190 @@
+/* fsi.h - C ABI of the MI355X (gfx950) monolithic Newton-Krylov-Schwarz FSI step.
+ *
+ * Method: Kong, Kheyfets, Finol, Cai, "Simulation of unsteady blood flows in a
+ * patient-specific compliant pulmonary artery with a highly parallel monolithically
+ * coupled fluid-structure interaction algorithm" (arXiv 1810.04289).
+ *
+ * One implicit backward-Euler step (§2.2, eq. (9)) is the root of F(y) = 0 (eq. (10)).
+ * It is found by inexact Newton with backtracking (§3, eq. (11)); each Newton direction
+ * solves J dy = -F (eq. (12)) with restarted GMRES (eq. (13)), right-preconditioned by
+ * restricted additive Schwarz (eq. (16)) whose subdomain solver is a block incomplete LU
+ * factorization ILU(l) (§3, §4.3).
+ *
+ * Unknowns: vertex-major, 7 per vertex [u_x u_y u_z p d_x d_y d_z], n = 7 * nverts.
+ *   u  fluid velocity at fluid vertices, wall velocity at wall vertices, shared at
+ *      interface vertices (strong coupling, §2.2 eqs. (6)-(7));
+ *   p  pressure (a dummy row p = 0 at wall-only vertices);
+ *   d  mesh displacement at fluid vertices, wall displacement at wall vertices, shared at
+ *      interface vertices.
+ * Jacobian: block CSR with 7x7 row-major FP64 blocks, int32 indices, sorted columns,
+ * diagonal always present, block (a,b) present iff a and b share a tetrahedron.
+ *
+ * Conventions for every entry point:
+ *  - returns fsi_status; no exception, exit or abort crosses this boundary;
+ *  - pointers marked (dev) are device pointers owned by the caller, valid for the call;
+ *    pointers marked (host) are host pointers owned by the caller;
+ *  - all device work is ordered on the HIP stream given to fsi_create; every entry point
+ *    returns after the stream work it issued has finished (host-side decisions of Newton
+ *    and GMRES need the results anyway);
+ *  - a failed call leaves a message readable through fsi_last_error.
+ */
+#ifndef FSI_H
+#define FSI_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSI_OK = 0,
+  FSI_ERR_ARG = 1,        /* bad argument, or a call out of order */
+  FSI_ERR_MESH = 2,       /* inconsistent mesh (index out of range, orphan vertex, ...) */
+  FSI_ERR_OOM = 3,        /* device or host allocation failed */
+  FSI_ERR_HIP = 4,        /* a HIP runtime call failed */
+  FSI_ERR_INVERTED = 5,   /* a fluid element with non-positive current volume, or det F <= 0 */
+  FSI_ERR_ZERO_PIVOT = 6, /* a singular 7x7 pivot block in the subdomain factorization */
+  FSI_ERR_DIVERGED = 7    /* Newton reached its iteration limit or the line search failed */
+} fsi_status;
+
+/* Boundary face tags. */
+enum { FSI_TAG_NONE = 0, FSI_TAG_FLUID_INLET = 1, FSI_TAG_FLUID_OUTLET = 2,
+       FSI_TAG_SOLID_RING_IN = 3, FSI_TAG_SOLID_RING_OUT = 4, FSI_TAG_WALL_OUTER = 5 };
+
+/* Mesh (§2.1, §4.8): reference coordinates, positively oriented tetrahedra split into
+ * fluid and wall elements, tagged boundary triangles.  Deep-copied by fsi_create. */
+typedef struct {
+  int32_t nverts, ntets, nbfaces;
+  const double *X;           /* (host) [nverts][3] reference coordinates, cm */
+  const int32_t *tets;       /* (host) [ntets][4] */
+  const int8_t *tet_domain;  /* (host) [ntets] 0 fluid, 1 wall */
+  const int32_t *bfaces;     /* (host) [nbfaces][3] */
+  const int8_t *bface_tag;   /* (host) [nbfaces] FSI_TAG_* */
+} fsi_mesh;
+
+/* Material constants (cgs; §2.1 and §4.1): fluid density and dynamic viscosity, wall
+ * density, Young's modulus, Poisson ratio, damping, and the inverse-estimate constant of
+ * the stabilization parameter. */
+typedef struct { double rho_f, mu_f, rho_s, E_s, nu_s, eta_s, C_I; } fsi_physics;
+
+/* Solver options (§3, §4).  Defaults of the paper: overlap 1, Newton rtol 1e-6, GMRES
+ * rtol 1e-3, Jacobian lag 1, subdomain ILU(1), RCM subdomain ordering. */
+typedef struct {
+  int32_t nsub;             /* number of Schwarz subdomains (>= 1) */
+  int32_t overlap;          /* delta: layers of vertex-graph neighbours added (>= 0) */
+  int32_t ilu_level;        /* l of ILU(l), 0..8 */
+  int32_t ordering;         /* 0 = reverse Cuthill-McKee (the only ordering) */
+  const int32_t *part;      /* (host) [nverts] subdomain of each vertex, or NULL for
+                               recursive coordinate bisection */
+  int32_t gmres_restart;    /* 1..200 */
+  int32_t gmres_maxit;      /* total GMRES iterations per solve */
+  double gmres_rtol;
+  double newton_rtol, newton_atol;
+  int32_t newton_maxit, jac_lag;
+  double ls_c;              /* Armijo constant of the backtracking line search */
+  int32_t ls_max_halvings;
+  int32_t precision;        /* 0 = FP64 everywhere */
+} fsi_opts;
+
+typedef struct {
+  int32_t iters, restarts, converged, pad;
+  double rnorm0, rnorm_est, rnorm_true;
+} fsi_lin_stats;
+
+#define FSI_MAX_NEWTON 64
+/* Per-step statistics; the six phase timers carry the paper's event names (Table 7). */
+typedef struct {
+  int32_t newton_iters, linear_iters, line_search_cuts, converged;
+  double fnorm0, fnorm;
+  double t_funceval, t_jaceval, t_pcsetup, t_pcapply, t_kspsolve, t_kspsetup; /* seconds */
+  double fnorm_hist[FSI_MAX_NEWTON];
+  double alpha_hist[FSI_MAX_NEWTON];
+  int32_t lin_hist[FSI_MAX_NEWTON];
+} fsi_step_stats;
+
+typedef struct fsi_solver fsi_solver;
+
+/* Build the solver: copies the mesh, classifies vertices (interface triangles by the
+ * interface reconstruction of §4.8, Algorithm 1), builds the block pattern, the element
+ * scatter maps, the partition, the overlapping subdomains (§3), their RCM order (§4.5),
+ * the ILU(l) fill pattern and level schedules, and allocates device memory.
+ * hip_stream: a hipStream_t (NULL = the null stream).  Errors: ARG, MESH, OOM, HIP. */
+fsi_status fsi_create(const fsi_mesh *mesh, const fsi_physics *phys, const fsi_opts *opts,
+                      void *hip_stream, fsi_solver **out);
+fsi_status fsi_destroy(fsi_solver *s);
+fsi_status fsi_sizes(const fsi_solver *s, int64_t *n, int64_t *nnzb);
+const char *fsi_last_error(const fsi_solver *s);
+
+/* Data of one backward-Euler step (§2.2 eq. (9)): time t_n, step dt > 0, previous state
+ * y_old (dev, n), Dirichlet values g (dev, n; used on Dirichlet rows, forced to zero on
+ * clamped wall rings), nodal body force (dev, [nverts][3], or NULL), and an optional
+ * extra Dirichlet mask (host, n bytes, 1 = Dirichlet with value g; NULL = none).
+ * Dirichlet rows from the tags: inlet u = g and d = 0, outlets d = 0, wall rings u = d = 0. */
+fsi_status fsi_set_step(fsi_solver *s, double t_n, double dt, const double *y_old,
+                        const double *g, const double *body_force, const uint8_t *extra_mask);
+
+/* Step setup (a Newton guess with the Dirichlet values and the dummy pressures written). */
+fsi_status fsi_impose_dirichlet(fsi_solver *s, double *y /* dev, n, in/out */);
+
+/* F(y) (eq. (10)): dt * (element residual) on equation rows, y - g on Dirichlet rows,
+ * (d - d_old) - dt u on kinematic rows, p on dummy rows.  Error INVERTED if an element
+ * inverts. */
+fsi_status fsi_residual(fsi_solver *s, const double *y /* dev, n */, double *F /* dev, n */);
+
+/* Exact Jacobian J = dF/dy at y (§3) into the solver's block matrix. */
+fsi_status fsi_jacobian(fsi_solver *s, const double *y /* dev, n */);
+/* Copy the block matrix to host arrays sized by fsi_sizes (any pointer may be NULL). */
+fsi_status fsi_jacobian_get(const fsi_solver *s, int32_t *rowptr /* host, nverts+1 */,
+                            int32_t *colind /* host, nnzb */, double *vals /* host, nnzb*49 */);
+
+/* Replace the values of the solver's block matrix by caller-supplied ones (same pattern as
+ * fsi_jacobian_get reports), e.g. a Jacobian assembled elsewhere.  Marks the matrix ready
+ * for fsi_spmv / fsi_pc_setup. */
+fsi_status fsi_jacobian_set(fsi_solver *s, const double *vals /* host, nnzb*49 */);
+
+/* y = J x with the current Jacobian. */
+fsi_status fsi_spmv(fsi_solver *s, const double *x /* dev, n */, double *y /* dev, n */);
+
+/* Schwarz setup (§3 eqs. (15)-(16)): gather every subdomain matrix from J and factor it
+ * by block ILU(l).  Error ZERO_PIVOT on a singular pivot block. */
+fsi_status fsi_pc_setup(fsi_solver *s);
+/* z = B^{-1} v = sum_i (R_i^0)^T (L_i U_i)^{-1} R_i^delta v. */
+fsi_status fsi_pc_apply(fsi_solver *s, const double *v /* dev, n */, double *z /* dev, n */);
+
+/* Right-preconditioned restarted GMRES on J x = rhs from x0 = 0 (classical Gram-Schmidt
+ * twice, Givens rotations).  Non-convergence is reported in st->converged, not as an
+ * error. */
+fsi_status fsi_gmres(fsi_solver *s, const double *rhs /* dev, n */, double *x /* dev, n */,
+                     fsi_lin_stats *st /* host, may be NULL */);
+
+/* One implicit step: Newton from the guess y (Dirichlet values imposed first) to
+ * ||F|| <= max(newton_rtol ||F_0||, newton_atol).  y (dev, n) is overwritten with the
+ * result.  Error DIVERGED if the iteration limit is hit or the line search fails. */
+fsi_status fsi_newton_solve(fsi_solver *s, double *y, fsi_step_stats *st /* host, may be NULL */);
+
+/* ---- introspection (host copies; for tests and diagnostics) ---- */
+/* vkind[nverts]: 0 fluid, 1 interface, 2 wall; rowkind[n]: 0 element, 1 Dirichlet,
+ * 2 kinematic, 3 dummy; interface triangles from Algorithm 1 as [n_iface][3]. */
+fsi_status fsi_topology_get(const fsi_solver *s, int8_t *vkind, uint8_t *rowkind,
+                            int32_t *n_iface, int32_t *iface_faces);
+fsi_status fsi_pc_sizes(const fsi_solver *s, int32_t *nsub, int64_t *nloc_rows,
+                        int64_t *nloc_blocks, int64_t *nlevels_total);
+/* Partition, RCM-ordered subdomain vertex lists, local block patterns, and (after
+ * fsi_pc_setup) the factors: strict L blocks (unit diagonal implied), strict U blocks,
+ * inverted diagonal blocks in the diagonal positions, and the U diagonal blocks before
+ * inversion (udiag). */
+fsi_status fsi_pc_get(const fsi_solver *s, int32_t *part, int32_t *sub_ptr, int32_t *sub_verts,
+                      int32_t *sub_nowned, int64_t *blk_ptr, int32_t *lrowptr, int32_t *lcolind,
+                      double *factors, double *udiag);
+
+/* ---- kernel timing (HIP events on the solver's stream) ----
+ * fsi_prof_enable(s, 1) starts recording an event pair around every launch of the timed
+ * kernels; fsi_prof_get returns the summed duration (ms) and launch count for a kernel
+ * name: "ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid",
+ * "jac_gather", "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate". */
+fsi_status fsi_prof_enable(fsi_solver *s, int32_t on);
+fsi_status fsi_prof_get(fsi_solver *s, const char *kernel, double *total_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,774 @@
+// C ABI of the HIP FSI library (declared in include/fsi.h): solver lifetime, uploads,
+// the host drivers of GMRES and Newton, introspection and kernel timing.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "fsi_internal.hpp"
+
+using namespace fsi;
+
+namespace {
+
+struct Fail {
+  fsi_status st;
+};
+
+inline void hip_ok(fsi_solver* s, hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    s->err = std::string(what) + ": " + hipGetErrorString(e);
+    throw Fail{e == hipErrorOutOfMemory ? FSI_ERR_OOM : FSI_ERR_HIP};
+  }
+}
+
+template <class T>
+T* dalloc(fsi_solver* s, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hip_ok(s, hipMalloc(&p, count * sizeof(T)), "hipMalloc");
+  s->allocs.push_back(p);
+  return (T*)p;
+}
+
+template <class T>
+T* upload(fsi_solver* s, const std::vector<T>& v) {
+  T* p = dalloc<T>(s, v.size());
+  if (!v.empty()) hip_ok(s, hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return p;
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void sync(fsi_solver* s) { hip_ok(s, hipStreamSynchronize(s->stream), "stream sync"); }
+
+// ||a||_2 (deterministic reduction), read back to the host
+double norm2(fsi_solver* s, const double* a) {
+  hip_ok(s, launch_dot_partial(s, a, a, s->n, s->hdev + 3 * (kMaxRestart + 8)), "dot");
+  hip_ok(s, hipMemcpyAsync(s->pinned, s->hdev + 3 * (kMaxRestart + 8), sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream), "readback");
+  sync(s);
+  return std::sqrt(s->pinned[0]);
+}
+
+void clear_flags(fsi_solver* s) {
+  hip_ok(s, hipMemsetAsync(s->flags, 0, 4 * sizeof(int32_t), s->stream), "memset flags");
+}
+
+int32_t read_flag(fsi_solver* s, int which) {
+  int32_t v = 0;
+  hip_ok(s, hipMemcpyAsync(&s->pinned[200], s->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+         "flag readback");
+  sync(s);
+  std::memcpy(&v, (char*)&s->pinned[200] + 4 * which, 4);
+  return v;
+}
+
+fsi_status residual_impl(fsi_solver* s, const double* y, double* F) {
+  clear_flags(s);
+  hip_ok(s, launch_residual(s, y, F), "residual");
+  if (read_flag(s, 0)) {
+    s->err = "inverted element";
+    return FSI_ERR_INVERTED;
+  }
+  return FSI_OK;
+}
+
+fsi_status jacobian_impl(fsi_solver* s, const double* y) {
+  clear_flags(s);
+  hip_ok(s, launch_jacobian(s, y), "jacobian");
+  if (read_flag(s, 0)) {
+    s->err = "inverted element";
+    return FSI_ERR_INVERTED;
+  }
+  s->jac_ready = true;
+  s->pc_ready = false;
+  return FSI_OK;
+}
+
+fsi_status pc_setup_impl(fsi_solver* s) {
+  if (!s->jac_ready) {
+    s->err = "pc_setup before jacobian";
+    return FSI_ERR_ARG;
+  }
+  clear_flags(s);
+  hip_ok(s, launch_pc_setup(s), "pc_setup");
+  if (read_flag(s, 1)) {
+    s->err = "zero pivot in a subdomain factorization";
+    return FSI_ERR_ZERO_PIVOT;
+  }
+  s->pc_ready = true;
+  return FSI_OK;
+}
+
+// Right-preconditioned restarted GMRES (§3 eq. (13)); classical Gram-Schmidt applied twice,
+// Givens rotations rho = hypot(a,b), c = a/rho, s = b/rho; happy breakdown when
+// h_{j+1,j} <= 1e-14 ||h||; stop when |g_{j+1}| <= rtol ||b||.
+fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* st, double* t_pc) {
+  const int64_t n = s->n;
+  const int m = s->opts.gmres_restart, maxit = s->opts.gmres_maxit;
+  fsi_lin_stats L{};
+  hip_ok(s, hipMemsetAsync(x, 0, n * sizeof(double), s->stream), "memset x");
+  const double bnorm = norm2(s, b);
+  L.rnorm0 = bnorm;
+  if (bnorm == 0.0) {
+    L.converged = 1;
+    if (st) *st = L;
+    return FSI_OK;
+  }
+  const double target = s->opts.gmres_rtol * bnorm;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m + 1);
+  auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  double* hA = s->hdev;                      // first Gram-Schmidt pass
+  double* hB = s->hdev + (kMaxRestart + 8);  // second pass
+  double* hn2 = s->hdev + 2 * (kMaxRestart + 8);
+  hip_ok(s, hipMemcpyAsync(s->r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream), "copy b");
+  int its = 0;
+  bool done = false;
+  hipEvent_t e0, e1;
+  hip_ok(s, hipEventCreate(&e0), "event");
+  hip_ok(s, hipEventCreate(&e1), "event");
+  auto timed_pc = [&](const double* v, double* zz) {
+    hip_ok(s, hipEventRecord(e0, s->stream), "event");
+    hip_ok(s, launch_pc_apply(s, v, zz), "pc_apply");
+    hip_ok(s, hipEventRecord(e1, s->stream), "event");
+    hip_ok(s, hipEventSynchronize(e1), "event");
+    float ms = 0.f;
+    hip_ok(s, hipEventElapsedTime(&ms, e0, e1), "event");
+    if (t_pc) *t_pc += ms * 1e-3;
+  };
+  while (!done) {
+    const double beta = norm2(s, s->r);
+    hip_ok(s, launch_scale(s, 1.0 / beta, s->r, s->Vb, n), "scale");
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = -1;
+    for (int j = 0; j < m; ++j) {
+      double* Vj = s->Vb + (size_t)j * n;
+      timed_pc(Vj, s->z);
+      hip_ok(s, launch_spmv(s, s->z, s->w), "spmv");
+      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hA), "mdot");
+      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hA, s->w, n), "vupdate");
+      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hB), "mdot");
+      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hB, s->w, n), "vupdate");
+      hip_ok(s, launch_dot_partial(s, s->w, s->w, n, hn2), "norm");
+      hip_ok(s, hipMemcpyAsync(s->pinned, s->hdev, 3 * (kMaxRestart + 8) * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream), "h readback");
+      sync(s);
+      const double* ha = s->pinned;
+      const double* hb = s->pinned + (kMaxRestart + 8);
+      double hsum2 = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        Hij(i, j) = ha[i] + hb[i];
+        hsum2 += Hij(i, j) * Hij(i, j);
+      }
+      const double hn = std::sqrt(s->pinned[2 * (kMaxRestart + 8)]);
+      Hij(j + 1, j) = hn;
+      const bool breakdown = hn <= 1e-14 * std::sqrt(hsum2 + hn * hn);
+      for (int i = 0; i < j; ++i) {
+        const double a = Hij(i, j), bq = Hij(i + 1, j);
+        Hij(i, j) = cs[i] * a + sn[i] * bq;
+        Hij(i + 1, j) = -sn[i] * a + cs[i] * bq;
+      }
+      const double a = Hij(j, j), bq = Hij(j + 1, j);
+      const double rho = std::hypot(a, bq);
+      cs[j] = a / rho;
+      sn[j] = bq / rho;
+      Hij(j, j) = rho;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      if (!breakdown) hip_ok(s, launch_scale(s, 1.0 / hn, s->w, s->Vb + (size_t)(j + 1) * n, n), "scale");
+      L.rnorm_est = std::fabs(g[j + 1]);
+      jend = j;
+      if (L.rnorm_est <= target) {
+        L.converged = 1;
+        done = true;
+        break;
+      }
+      if (breakdown || its >= maxit) {
+        done = true;
+        break;
+      }
+    }
+    for (int i = jend; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k <= jend; ++k) acc -= Hij(i, k) * yv[k];
+      yv[i] = acc / Hij(i, i);
+    }
+    std::memcpy(s->pinned, yv.data(), (jend + 1) * sizeof(double));
+    hip_ok(s, hipMemcpyAsync(s->yvdev, s->pinned, (jend + 1) * sizeof(double), hipMemcpyHostToDevice, s->stream),
+           "y upload");
+    hip_ok(s, launch_vcombine(s, s->Vb, jend + 1, s->yvdev, s->tmp, n), "vcombine");
+    timed_pc(s->tmp, s->z);
+    hip_ok(s, launch_axpby(s, 1.0, x, 1.0, s->z, x, n), "axpby");
+    if (!done) {
+      ++L.restarts;
+      hip_ok(s, launch_spmv(s, x, s->w), "spmv");
+      hip_ok(s, launch_axpby(s, 1.0, b, -1.0, s->w, s->r, n), "axpby");
+    }
+  }
+  hip_ok(s, launch_spmv(s, x, s->w), "spmv");
+  hip_ok(s, launch_axpby(s, 1.0, b, -1.0, s->w, s->w, n), "axpby");
+  L.rnorm_true = norm2(s, s->w);
+  L.iters = its;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) *st = L;
+  return FSI_OK;
+}
+
+// Inexact Newton with backtracking (§3 eqs. (11)-(12)).
+fsi_status newton_impl(fsi_solver* s, double* y, fsi_step_stats* st) {
+  const int64_t n = s->n;
+  fsi_step_stats S;
+  std::memset(&S, 0, sizeof(S));
+  hip_ok(s, launch_impose(s, y), "impose");
+  double t0 = now();
+  fsi_status rc = residual_impl(s, y, s->F);
+  S.t_funceval += now() - t0;
+  if (rc) {
+    if (st) *st = S;
+    return rc;
+  }
+  const double f0 = norm2(s, s->F);
+  double fk = f0;
+  S.fnorm0 = f0;
+  S.fnorm_hist[0] = f0;
+  int k = 0;
+  fsi_status status = FSI_OK;
+  for (;;) {
+    if (fk <= std::max(s->opts.newton_rtol * f0, s->opts.newton_atol)) {
+      S.converged = 1;
+      break;
+    }
+    if (k >= s->opts.newton_maxit) {
+      status = FSI_ERR_DIVERGED;
+      s->err = "Newton iteration limit reached";
+      break;
+    }
+    if (k % std::max(1, s->opts.jac_lag) == 0) {
+      t0 = now();
+      rc = jacobian_impl(s, y);
+      S.t_jaceval += now() - t0;
+      if (rc) {
+        status = rc;
+        break;
+      }
+      t0 = now();
+      rc = pc_setup_impl(s);
+      sync(s);
+      S.t_pcsetup += now() - t0;
+      if (rc) {
+        status = rc;
+        break;
+      }
+    }
+    hip_ok(s, launch_scale(s, -1.0, s->F, s->rhs, n), "negate");
+    fsi_lin_stats ls{};
+    t0 = now();
+    double tpc = 0.0;
+    gmres_impl(s, s->rhs, s->dy, &ls, &tpc);
+    S.t_kspsolve += now() - t0;
+    S.t_pcapply += tpc;
+    S.linear_iters += ls.iters;
+    if (k < FSI_MAX_NEWTON) S.lin_hist[k] = ls.iters;
+    double alpha = 1.0;
+    bool accepted = false;
+    for (int hcut = 0; hcut <= s->opts.ls_max_halvings; ++hcut) {
+      hip_ok(s, launch_axpby(s, 1.0, y, alpha, s->dy, s->yt, n), "trial");
+      t0 = now();
+      rc = residual_impl(s, s->yt, s->Ft);
+      if (rc == FSI_OK) {
+        const double ft = norm2(s, s->Ft);
+        S.t_funceval += now() - t0;
+        if (ft <= (1.0 - s->opts.ls_c * alpha) * fk) {
+          accepted = true;
+          fk = ft;
+          break;
+        }
+      } else {
+        S.t_funceval += now() - t0;
+      }
+      alpha *= 0.5;
+      S.line_search_cuts++;
+    }
+    if (!accepted) {
+      status = FSI_ERR_DIVERGED;
+      s->err = "line search failed";
+      break;
+    }
+    hip_ok(s, hipMemcpyAsync(y, s->yt, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream), "accept");
+    std::swap(s->F, s->Ft);
+    ++k;
+    if (k < FSI_MAX_NEWTON) {
+      S.fnorm_hist[k] = fk;
+      S.alpha_hist[k - 1] = alpha;
+    }
+  }
+  sync(s);
+  S.newton_iters = k;
+  S.fnorm = fk;
+  if (st) *st = S;
+  return status;
+}
+
+fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* o, void* stream, fsi_solver* s) {
+  HostSetup& h = s->h;
+  h.V = m->nverts;
+  h.E = m->ntets;
+  h.B = m->nbfaces;
+  h.X.assign(m->X, m->X + 3 * (size_t)h.V);
+  h.tets.assign(m->tets, m->tets + 4 * (size_t)h.E);
+  h.dom.assign(m->tet_domain, m->tet_domain + h.E);
+  if (h.B > 0) {
+    h.bfaces.assign(m->bfaces, m->bfaces + 3 * (size_t)h.B);
+    h.btag.assign(m->bface_tag, m->bface_tag + h.B);
+  }
+  for (int32_t v : h.tets)
+    if (v < 0 || v >= h.V) {
+      s->err = "tet index out of range";
+      return FSI_ERR_MESH;
+    }
+  for (int32_t v : h.bfaces)
+    if (v < 0 || v >= h.V) {
+      s->err = "boundary face index out of range";
+      return FSI_ERR_MESH;
+    }
+  for (int8_t d : h.dom)
+    if (d != 0 && d != 1) {
+      s->err = "tet_domain must be 0 or 1";
+      return FSI_ERR_MESH;
+    }
+  s->ph = *ph;
+  s->opts = *o;
+  s->opts.part = nullptr;
+  s->stream = (hipStream_t)stream;
+  std::string e = build_topology(h);
+  if (!e.empty()) {
+    s->err = e;
+    return FSI_ERR_MESH;
+  }
+  e = build_subdomains(h, *o);
+  if (!e.empty()) {
+    s->err = e;
+    return FSI_ERR_ARG;
+  }
+  s->n = 7 * (int64_t)h.V;
+  s->nnzb = (int64_t)h.colind.size();
+  s->R = (int64_t)h.lglob.size();
+  s->NB = (int64_t)h.lcol.size();
+  std::vector<int32_t> blkrow(s->nnzb);
+  for (int v = 0; v < h.V; ++v)
+    for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) blkrow[k] = v;
+
+  s->X = upload(s, h.X);
+  s->tets = upload(s, h.tets);
+  s->fluid_elems = upload(s, h.fluid_elems);
+  s->solid_elems = upload(s, h.solid_elems);
+  s->vinc_ptr = upload(s, h.vinc_ptr);
+  s->vinc = upload(s, h.vinc);
+  s->bctr_ptr = upload(s, h.bctr_ptr);
+  s->bctr = upload(s, h.bctr);
+  s->rowptr = upload(s, h.rowptr);
+  s->colind = upload(s, h.colind);
+  s->blkrow = upload(s, blkrow);
+  s->vals = dalloc<double>(s, (size_t)s->nnzb * 49);
+  s->elemR = dalloc<double>(s, (size_t)h.E * 28);
+  s->elemJ = dalloc<double>(s, (size_t)h.E * 784);
+  s->rowkind = dalloc<uint8_t>(s, s->n);
+  s->gval = dalloc<double>(s, s->n);
+  s->yold = dalloc<double>(s, s->n);
+  s->bforce = dalloc<double>(s, 3 * (size_t)h.V);
+  s->lglob = upload(s, h.lglob);
+  s->lowned = upload(s, h.lowned);
+  s->lrowptr = upload(s, h.lrowptr);
+  s->lcol = upload(s, h.lcol);
+  s->lsrc = upload(s, h.lsrc);
+  s->ldiag = upload(s, h.ldiag);
+  s->fwd_sub_lvl = upload(s, h.fwd_sub_lvl);
+  s->fwd_lvl_ptr = upload(s, h.fwd_lvl_ptr);
+  s->fwd_rows = upload(s, h.fwd_rows);
+  s->bwd_sub_lvl = upload(s, h.bwd_sub_lvl);
+  s->bwd_lvl_ptr = upload(s, h.bwd_lvl_ptr);
+  s->bwd_rows = upload(s, h.bwd_rows);
+  s->kent_ptr = upload(s, h.kent_ptr);
+  s->kent_ik = upload(s, h.kent_ik);
+  s->kent_dk = upload(s, h.kent_dk);
+  s->kent_tptr = upload(s, h.kent_tptr);
+  s->tri_kj = upload(s, h.tri_kj);
+  s->tri_ij = upload(s, h.tri_ij);
+  s->sub_row_off = upload(s, h.sub_row_off);
+  s->fac = dalloc<double>(s, (size_t)s->NB * 49);
+  s->udiag = dalloc<double>(s, (size_t)s->R * 49);
+  s->ylocal = dalloc<double>(s, (size_t)s->R * 7);
+  const int mrs = s->opts.gmres_restart;
+  s->Vb = dalloc<double>(s, (size_t)(mrs + 1) * s->n);
+  s->w = dalloc<double>(s, s->n);
+  s->z = dalloc<double>(s, s->n);
+  s->r = dalloc<double>(s, s->n);
+  s->tmp = dalloc<double>(s, s->n);
+  s->partial = dalloc<double>(s, (size_t)kRedBlocks * 32);
+  s->hdev = dalloc<double>(s, 4 * (kMaxRestart + 8));
+  s->yvdev = dalloc<double>(s, kMaxRestart + 8);
+  s->F = dalloc<double>(s, s->n);
+  s->Ft = dalloc<double>(s, s->n);
+  s->yt = dalloc<double>(s, s->n);
+  s->dy = dalloc<double>(s, s->n);
+  s->rhs = dalloc<double>(s, s->n);
+  s->flags = dalloc<int32_t>(s, 4);
+  hip_ok(s, hipHostMalloc((void**)&s->pinned, 4 * (kMaxRestart + 8) * sizeof(double), hipHostMallocDefault),
+         "hipHostMalloc");
+  hip_ok(s, hipMemset(s->flags, 0, 4 * sizeof(int32_t)), "memset");
+  hip_ok(s, hipMemset(s->hdev, 0, 4 * (kMaxRestart + 8) * sizeof(double)), "memset");
+  hip_ok(s, hipDeviceSynchronize(), "sync");
+  return FSI_OK;
+}
+
+fsi_status guard(fsi_solver* s, fsi_status (*fn)(fsi_solver*, void*), void* arg) {
+  try {
+    return fn(s, arg);
+  } catch (const Fail& f) {
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    s->err = "host allocation failed";
+    return FSI_ERR_OOM;
+  } catch (...) {
+    s->err = "unexpected exception";
+    return FSI_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+namespace fsi {
+void prof_begin(fsi_solver* s, const char* name, hipEvent_t* ev) {
+  (void)name;
+  hipEvent_t a;
+  if (!s->event_pool.empty()) {
+    a = s->event_pool.back();
+    s->event_pool.pop_back();
+  } else {
+    (void)hipEventCreate(&a);
+  }
+  (void)hipEventRecord(a, s->stream);
+  *ev = a;
+}
+void prof_end(fsi_solver* s, const char* name, hipEvent_t a) {
+  hipEvent_t b;
+  if (!s->event_pool.empty()) {
+    b = s->event_pool.back();
+    s->event_pool.pop_back();
+  } else {
+    (void)hipEventCreate(&b);
+  }
+  (void)hipEventRecord(b, s->stream);
+  s->prof_events.push_back(ProfEntry{name, a, b});
+}
+}  // namespace fsi
+
+extern "C" {
+
+fsi_status fsi_create(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* o, void* stream, fsi_solver** out) {
+  if (!m || !ph || !o || !out || m->nverts <= 0 || m->ntets <= 0 || !m->X || !m->tets || !m->tet_domain ||
+      (m->nbfaces > 0 && (!m->bfaces || !m->bface_tag)) || m->nbfaces < 0)
+    return FSI_ERR_ARG;
+  if (o->nsub <= 0 || o->nsub > m->nverts || o->overlap < 0 || o->ilu_level < 0 || o->ilu_level > 8 ||
+      o->gmres_restart <= 0 || o->gmres_restart > kMaxRestart || o->gmres_maxit <= 0 || o->ordering != 0 ||
+      o->precision != 0 || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
+    return FSI_ERR_ARG;
+  fsi_solver* s = new (std::nothrow) fsi_solver();
+  if (!s) return FSI_ERR_OOM;
+  struct A {
+    const fsi_mesh* m;
+    const fsi_physics* ph;
+    const fsi_opts* o;
+    void* st;
+  } a{m, ph, o, stream};
+  fsi_status rc = guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    return create_impl(a->m, a->ph, a->o, a->st, s);
+  }, &a);
+  if (rc) {
+    fsi_destroy(s);
+    return rc;
+  }
+  *out = s;
+  return FSI_OK;
+}
+
+fsi_status fsi_destroy(fsi_solver* s) {
+  if (!s) return FSI_OK;
+  (void)hipStreamSynchronize(s->stream);
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->pinned) (void)hipHostFree(s->pinned);
+  for (auto& e : s->prof_events) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (auto e : s->event_pool) (void)hipEventDestroy(e);
+  delete s;
+  return FSI_OK;
+}
+
+fsi_status fsi_sizes(const fsi_solver* s, int64_t* n, int64_t* nnzb) {
+  if (!s) return FSI_ERR_ARG;
+  if (n) *n = s->n;
+  if (nnzb) *nnzb = s->nnzb;
+  return FSI_OK;
+}
+
+const char* fsi_last_error(const fsi_solver* s) { return s ? s->err.c_str() : "null solver"; }
+
+fsi_status fsi_set_step(fsi_solver* s, double t_n, double dt, const double* y_old, const double* g,
+                        const double* bf, const uint8_t* extra_mask) {
+  if (!s || !y_old || !g || !(dt > 0.0) || !std::isfinite(dt)) return FSI_ERR_ARG;
+  struct A {
+    double t, dt;
+    const double *yo, *g, *bf;
+    const uint8_t* em;
+  } a{t_n, dt, y_old, g, bf, extra_mask};
+  return guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    const size_t n = s->n;
+    s->t = a->t;
+    s->dt = a->dt;
+    s->rowkind_host = s->h.rowkind_base;
+    if (a->em)
+      for (size_t i = 0; i < n; ++i)
+        if (a->em[i]) s->rowkind_host[i] = RK_DIR;
+    hip_ok(s, hipMemcpyAsync(s->rowkind, s->rowkind_host.data(), n, hipMemcpyHostToDevice, s->stream), "rowkind");
+    hip_ok(s, hipMemcpyAsync(s->yold, a->yo, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream), "yold");
+    hip_ok(s, hipMemcpyAsync(s->gval, a->g, n * sizeof(double), hipMemcpyDeviceToDevice, s->stream), "g");
+    // clamped wall rings take the value zero whatever g holds there
+    std::vector<double> fz;
+    bool any = false;
+    for (size_t i = 0; i < n && !any; ++i) any = s->h.forced_zero[i] && s->rowkind_host[i] == RK_DIR;
+    if (any) {
+      sync(s);
+      fz.resize(n);
+      hip_ok(s, hipMemcpy(fz.data(), s->gval, n * sizeof(double), hipMemcpyDeviceToHost), "g down");
+      for (size_t i = 0; i < n; ++i)
+        if (s->h.forced_zero[i]) fz[i] = 0.0;
+      hip_ok(s, hipMemcpy(s->gval, fz.data(), n * sizeof(double), hipMemcpyHostToDevice), "g up");
+    }
+    s->has_bforce = a->bf != nullptr;
+    if (a->bf)
+      hip_ok(s, hipMemcpyAsync(s->bforce, a->bf, 3 * (size_t)s->h.V * sizeof(double), hipMemcpyDeviceToDevice,
+                               s->stream), "bforce");
+    sync(s);
+    s->has_step = true;
+    s->jac_ready = false;
+    s->pc_ready = false;
+    return FSI_OK;
+  }, &a);
+}
+
+fsi_status fsi_impose_dirichlet(fsi_solver* s, double* y) {
+  if (!s || !y || !s->has_step) return FSI_ERR_ARG;
+  return guard(s, [](fsi_solver* s, void* p) {
+    hip_ok(s, launch_impose(s, (double*)p), "impose");
+    sync(s);
+    return FSI_OK;
+  }, y);
+}
+
+fsi_status fsi_residual(fsi_solver* s, const double* y, double* F) {
+  if (!s || !y || !F || !s->has_step) return FSI_ERR_ARG;
+  const double* a[2] = {y, F};
+  return guard(s, [](fsi_solver* s, void* p) {
+    const double** a = (const double**)p;
+    return residual_impl(s, a[0], (double*)a[1]);
+  }, a);
+}
+
+fsi_status fsi_jacobian(fsi_solver* s, const double* y) {
+  if (!s || !y || !s->has_step) return FSI_ERR_ARG;
+  return guard(s, [](fsi_solver* s, void* p) { return jacobian_impl(s, (const double*)p); }, (void*)y);
+}
+
+fsi_status fsi_jacobian_get(const fsi_solver* cs, int32_t* rowptr, int32_t* colind, double* vals) {
+  if (!cs) return FSI_ERR_ARG;
+  fsi_solver* s = const_cast<fsi_solver*>(cs);
+  if (rowptr) std::copy(s->h.rowptr.begin(), s->h.rowptr.end(), rowptr);
+  if (colind) std::copy(s->h.colind.begin(), s->h.colind.end(), colind);
+  if (vals) {
+    if (!s->jac_ready) return FSI_ERR_ARG;
+    return guard(s, [](fsi_solver* s, void* p) {
+      sync(s);
+      hip_ok(s, hipMemcpy(p, s->vals, (size_t)s->nnzb * 49 * sizeof(double), hipMemcpyDeviceToHost), "vals down");
+      return FSI_OK;
+    }, vals);
+  }
+  return FSI_OK;
+}
+
+fsi_status fsi_jacobian_set(fsi_solver* s, const double* vals) {
+  if (!s || !vals) return FSI_ERR_ARG;
+  return guard(s, [](fsi_solver* s, void* p) {
+    sync(s);
+    hip_ok(s, hipMemcpy(s->vals, p, (size_t)s->nnzb * 49 * sizeof(double), hipMemcpyHostToDevice), "vals up");
+    s->jac_ready = true;
+    s->pc_ready = false;
+    return FSI_OK;
+  }, (void*)vals);
+}
+
+fsi_status fsi_spmv(fsi_solver* s, const double* x, double* y) {
+  if (!s || !x || !y || !s->jac_ready) return FSI_ERR_ARG;
+  const double* a[2] = {x, y};
+  return guard(s, [](fsi_solver* s, void* p) {
+    const double** a = (const double**)p;
+    hip_ok(s, launch_spmv(s, a[0], (double*)a[1]), "spmv");
+    sync(s);
+    return FSI_OK;
+  }, a);
+}
+
+fsi_status fsi_pc_setup(fsi_solver* s) {
+  if (!s) return FSI_ERR_ARG;
+  return guard(s, [](fsi_solver* s, void*) {
+    fsi_status rc = pc_setup_impl(s);
+    sync(s);
+    return rc;
+  }, nullptr);
+}
+
+fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
+  if (!s || !v || !z || !s->pc_ready) return FSI_ERR_ARG;
+  const double* a[2] = {v, z};
+  return guard(s, [](fsi_solver* s, void* p) {
+    const double** a = (const double**)p;
+    hip_ok(s, launch_pc_apply(s, a[0], (double*)a[1]), "pc_apply");
+    sync(s);
+    return FSI_OK;
+  }, a);
+}
+
+fsi_status fsi_gmres(fsi_solver* s, const double* rhs, double* x, fsi_lin_stats* st) {
+  if (!s || !rhs || !x || !s->pc_ready) return FSI_ERR_ARG;
+  struct A {
+    const double* b;
+    double* x;
+    fsi_lin_stats* st;
+  } a{rhs, x, st};
+  return guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    fsi_status rc = gmres_impl(s, a->b, a->x, a->st, nullptr);
+    sync(s);
+    return rc;
+  }, &a);
+}
+
+fsi_status fsi_newton_solve(fsi_solver* s, double* y, fsi_step_stats* st) {
+  if (!s || !y || !s->has_step) return FSI_ERR_ARG;
+  struct A {
+    double* y;
+    fsi_step_stats* st;
+  } a{y, st};
+  return guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    return newton_impl(s, a->y, a->st);
+  }, &a);
+}
+
+fsi_status fsi_topology_get(const fsi_solver* s, int8_t* vkind, uint8_t* rowkind, int32_t* n_iface,
+                            int32_t* iface_faces) {
+  if (!s) return FSI_ERR_ARG;
+  if (vkind) std::copy(s->h.vkind.begin(), s->h.vkind.end(), vkind);
+  if (rowkind) {
+    const std::vector<uint8_t>& rk = s->has_step ? s->rowkind_host : s->h.rowkind_base;
+    std::copy(rk.begin(), rk.end(), rowkind);
+  }
+  if (n_iface) *n_iface = (int32_t)(s->h.iface.size() / 3);
+  if (iface_faces) std::copy(s->h.iface.begin(), s->h.iface.end(), iface_faces);
+  return FSI_OK;
+}
+
+fsi_status fsi_pc_sizes(const fsi_solver* s, int32_t* nsub, int64_t* nrows, int64_t* nblocks, int64_t* nlev) {
+  if (!s) return FSI_ERR_ARG;
+  if (nsub) *nsub = s->h.ns;
+  if (nrows) *nrows = s->R;
+  if (nblocks) *nblocks = s->NB;
+  if (nlev) *nlev = (int64_t)s->h.fwd_lvl_ptr.size() - 1;
+  return FSI_OK;
+}
+
+fsi_status fsi_pc_get(const fsi_solver* cs, int32_t* part, int32_t* sub_ptr, int32_t* sub_verts,
+                      int32_t* sub_nowned, int64_t* blk_ptr, int32_t* lrowptr, int32_t* lcolind, double* factors,
+                      double* udiag) {
+  if (!cs) return FSI_ERR_ARG;
+  fsi_solver* s = const_cast<fsi_solver*>(cs);
+  const HostSetup& h = s->h;
+  if (part) std::copy(h.part.begin(), h.part.end(), part);
+  if (sub_ptr) std::copy(h.sub_row_off.begin(), h.sub_row_off.end(), sub_ptr);
+  if (sub_verts) std::copy(h.lglob.begin(), h.lglob.end(), sub_verts);
+  if (sub_nowned) std::copy(h.sub_nowned.begin(), h.sub_nowned.end(), sub_nowned);
+  for (int i = 0; i < h.ns; ++i) {
+    const int r0 = h.sub_row_off[i], r1 = h.sub_row_off[i + 1];
+    const int b0 = h.lrowptr[r0];
+    if (blk_ptr) {
+      blk_ptr[i] = b0;
+      blk_ptr[i + 1] = h.lrowptr[r1];
+    }
+    if (lrowptr)  // per-subdomain local row pointers, concatenated (size R + ns)
+      for (int r = r0; r <= r1; ++r) lrowptr[r + i] = h.lrowptr[r] - b0;
+    if (lcolind)
+      for (int p = b0; p < h.lrowptr[r1]; ++p) lcolind[p] = h.lcol[p] - r0;
+  }
+  if ((factors || udiag) && !s->pc_ready) return FSI_ERR_ARG;
+  const double* a[2] = {factors, udiag};
+  if (factors || udiag)
+    return guard(s, [](fsi_solver* s, void* p) {
+      double** a = (double**)p;
+      sync(s);
+      if (a[0]) hip_ok(s, hipMemcpy(a[0], s->fac, (size_t)s->NB * 49 * sizeof(double), hipMemcpyDeviceToHost), "fac");
+      if (a[1]) hip_ok(s, hipMemcpy(a[1], s->udiag, (size_t)s->R * 49 * sizeof(double), hipMemcpyDeviceToHost), "ud");
+      return FSI_OK;
+    }, (void*)a);
+  return FSI_OK;
+}
+
+fsi_status fsi_prof_enable(fsi_solver* s, int32_t on) {
+  if (!s) return FSI_ERR_ARG;
+  (void)hipStreamSynchronize(s->stream);
+  for (auto& e : s->prof_events) {  // a new enable starts a fresh record
+    s->event_pool.push_back(e.a);
+    s->event_pool.push_back(e.b);
+  }
+  s->prof_events.clear();
+  s->prof = on != 0;
+  return FSI_OK;
+}
+
+fsi_status fsi_prof_get(fsi_solver* s, const char* kernel, double* total_ms, int64_t* count) {
+  if (!s || !kernel) return FSI_ERR_ARG;
+  struct A {
+    const char* name;
+    double* tot;
+    int64_t* cnt;
+  } a{kernel, total_ms, count};
+  return guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    sync(s);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& e : s->prof_events) {
+      if (e.name != a->name) continue;
+      float ms = 0.f;
+      hip_ok(s, hipEventElapsedTime(&ms, e.a, e.b), "event time");
+      tot += ms;
+      ++cnt;
+    }
+    if (a->tot) *a->tot = tot;
+    if (a->cnt) *a->cnt = cnt;
+    return FSI_OK;
+  }, &a);
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Internal state of the HIP FSI library: host-side setup products and the device-resident
+// data layout.  Every device array lives in HBM for the solver's lifetime; nothing is
+// re-uploaded per Newton step except the step data of fsi_set_step.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fsi.h"
+
+namespace fsi {
+
+enum : int8_t { VK_FLUID = 0, VK_IFACE = 1, VK_SOLID = 2 };
+enum : uint8_t { RK_ELEM = 0, RK_DIR = 1, RK_KIN = 2, RK_DUMMY = 3 };
+
+constexpr int kMaxRestart = 200;
+constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic sums
+
+// Host-side setup products (independent of any device state).
+struct HostSetup {
+  int V = 0, E = 0, B = 0;
+  std::vector<double> X;
+  std::vector<int32_t> tets;
+  std::vector<int8_t> dom;
+  std::vector<int32_t> bfaces;
+  std::vector<int8_t> btag;
+
+  std::vector<int8_t> vkind;
+  std::vector<uint8_t> rowkind_base, forced_zero;
+  std::vector<int32_t> iface;  // [n_iface][3]
+
+  std::vector<int32_t> rowptr, colind;          // block pattern
+  std::vector<int32_t> fluid_elems, solid_elems;
+  std::vector<int32_t> vinc_ptr, vinc;          // vertex -> (e*4 + local) ascending e
+  std::vector<int32_t> bctr_ptr, bctr;          // block -> (e*16 + la*4 + lb) ascending e
+
+  // Schwarz subdomains (concatenated; a "local row" is one vertex of one subdomain)
+  int ns = 0;
+  std::vector<int32_t> part;
+  std::vector<int32_t> sub_row_off;   // [ns+1]
+  std::vector<int32_t> sub_nowned;    // [ns]
+  std::vector<int32_t> lglob;         // [R] global vertex (RCM order inside each subdomain)
+  std::vector<uint8_t> lowned;        // [R]
+  std::vector<int32_t> lrowptr;       // [R+1] into the concatenated local blocks
+  std::vector<int32_t> lcol;          // [NB] column as a concatenated local row index
+  std::vector<int32_t> lsrc;          // [NB] block of J, or -1 for a fill block
+  std::vector<int32_t> ldiag;         // [R]
+  // level schedules: rows of level l of subdomain s are
+  // rows[lvl_ptr[sub_lvl[s] + l] .. lvl_ptr[sub_lvl[s] + l + 1])
+  std::vector<int32_t> fwd_sub_lvl, fwd_lvl_ptr, fwd_rows;
+  std::vector<int32_t> bwd_sub_lvl, bwd_lvl_ptr, bwd_rows;
+  // factorization work lists
+  std::vector<int32_t> kent_ptr;       // [R+1]
+  std::vector<int32_t> kent_ik, kent_dk, kent_tptr;  // [K], [K], [K+1]
+  std::vector<int32_t> tri_kj, tri_ij;               // [T]
+};
+
+std::string build_topology(HostSetup& h);
+std::string build_subdomains(HostSetup& h, const fsi_opts& o);
+
+struct ProfEntry {
+  std::string name;
+  hipEvent_t a, b;
+};
+
+}  // namespace fsi
+
+struct fsi_solver {
+  fsi::HostSetup h;
+  fsi_physics ph{};
+  fsi_opts opts{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int64_t n = 0, nnzb = 0, R = 0, NB = 0;
+
+  // mesh and maps
+  double* X = nullptr;
+  int32_t *tets = nullptr, *fluid_elems = nullptr, *solid_elems = nullptr;
+  int32_t *vinc_ptr = nullptr, *vinc = nullptr, *bctr_ptr = nullptr, *bctr = nullptr;
+  int32_t *rowptr = nullptr, *colind = nullptr, *blkrow = nullptr;
+  double* vals = nullptr;
+  double *elemR = nullptr, *elemJ = nullptr;
+  // step data
+  uint8_t* rowkind = nullptr;
+  double *gval = nullptr, *yold = nullptr, *bforce = nullptr;
+  bool has_bforce = false, has_step = false, jac_ready = false, pc_ready = false;
+  double t = 0.0, dt = 0.0;
+  std::vector<uint8_t> rowkind_host;
+  // Schwarz / ILU
+  int32_t *lglob = nullptr, *lrowptr = nullptr, *lcol = nullptr, *lsrc = nullptr, *ldiag = nullptr;
+  uint8_t* lowned = nullptr;
+  int32_t *fwd_sub_lvl = nullptr, *fwd_lvl_ptr = nullptr, *fwd_rows = nullptr;
+  int32_t *bwd_sub_lvl = nullptr, *bwd_lvl_ptr = nullptr, *bwd_rows = nullptr;
+  int32_t *kent_ptr = nullptr, *kent_ik = nullptr, *kent_dk = nullptr, *kent_tptr = nullptr;
+  int32_t *tri_kj = nullptr, *tri_ij = nullptr;
+  int32_t* sub_row_off = nullptr;
+  double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
+  // Krylov / Newton work vectors
+  double *Vb = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr;
+  double *partial = nullptr, *hdev = nullptr, *yvdev = nullptr;
+  double *F = nullptr, *Ft = nullptr, *yt = nullptr, *dy = nullptr, *rhs = nullptr;
+  int32_t* flags = nullptr;      // [0] inverted, [1] zero pivot
+  double* pinned = nullptr;      // host-pinned readback buffer (256 doubles)
+  std::vector<void*> allocs;
+
+  bool prof = false;
+  std::vector<fsi::ProfEntry> prof_events;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace fsi {
+// launchers (assembly.hip, linalg.hip, ilu.hip); all enqueue on s->stream
+hipError_t launch_residual(fsi_solver* s, const double* y, double* F);
+hipError_t launch_jacobian(fsi_solver* s, const double* y);
+hipError_t launch_impose(fsi_solver* s, double* y);
+hipError_t launch_spmv(fsi_solver* s, const double* x, double* y);
+hipError_t launch_pc_setup(fsi_solver* s);
+hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
+hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
+hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);
+hipError_t launch_vupdate(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n);
+hipError_t launch_vcombine(fsi_solver* s, const double* Vb, int nv, const double* y, double* out, int64_t n);
+hipError_t launch_axpby(fsi_solver* s, double a, const double* x, double b, const double* y, double* out, int64_t n);
+hipError_t launch_scale(fsi_solver* s, double a, const double* x, double* out, int64_t n);
+
+// profiling helpers (capi.hip)
+void prof_begin(fsi_solver* s, const char* name, hipEvent_t* ev_begin);
+void prof_end(fsi_solver* s, const char* name, hipEvent_t ev_begin);
+}  // namespace fsi
+
+#define FSI_PROF_LAUNCH(s, name, ...)                   \
+  do {                                                  \
+    hipEvent_t _pe = nullptr;                           \
+    if ((s)->prof) fsi::prof_begin((s), (name), &_pe);  \
+    __VA_ARGS__;                                        \
+    if ((s)->prof) fsi::prof_end((s), (name), _pe);     \
+  } while (0)

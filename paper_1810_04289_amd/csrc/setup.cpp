@@ -1,0 +1,438 @@
+// Host-side setup of the HIP FSI library: interface reconstruction, vertex and row
+// classes, the block pattern, element scatter maps, partition, overlapping subdomains,
+// reverse Cuthill-McKee, the ILU(l) fill pattern, level schedules and the factorization
+// work lists.  All of it runs once per mesh; the products are uploaded to HBM.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <numeric>
+#include <queue>
+
+#include "fsi_internal.hpp"
+
+namespace fsi {
+
+// Outward faces of a positively oriented tetrahedron.
+static const int kTetFace[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+
+std::string build_topology(HostSetup& h) {
+  const int V = h.V, E = h.E;
+  // ---- Algorithm 1 (§4.8): interface triangles.  Faces are matched by sorting the
+  // sorted vertex triples; a fluid face whose twin belongs to a wall element is an
+  // interface triangle.
+  struct Rec { int32_t a, b, c, e, f; };
+  std::vector<Rec> rec((size_t)E * 4);
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 4; ++f) {
+      int32_t v[3] = {h.tets[4 * e + kTetFace[f][0]], h.tets[4 * e + kTetFace[f][1]],
+                      h.tets[4 * e + kTetFace[f][2]]};
+      std::sort(v, v + 3);
+      rec[4 * (size_t)e + f] = {v[0], v[1], v[2], e, f};
+    }
+  std::sort(rec.begin(), rec.end(), [](const Rec& x, const Rec& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.e < y.e;
+  });
+  std::vector<int32_t> twin((size_t)E * 4, -1);  // element across each face
+  for (size_t i = 0; i < rec.size();) {
+    size_t j = i + 1;
+    while (j < rec.size() && rec[j].a == rec[i].a && rec[j].b == rec[i].b && rec[j].c == rec[i].c) ++j;
+    if (j - i > 2) return "a face is shared by more than two elements";
+    if (j - i == 2) {
+      twin[4 * (size_t)rec[i].e + rec[i].f] = rec[i + 1].e;
+      twin[4 * (size_t)rec[i + 1].e + rec[i + 1].f] = rec[i].e;
+    }
+    i = j;
+  }
+  h.iface.clear();
+  for (int e = 0; e < E; ++e) {
+    if (h.dom[e] != 0) continue;
+    for (int f = 0; f < 4; ++f) {
+      int o = twin[4 * (size_t)e + f];
+      if (o >= 0 && h.dom[o] == 1)
+        for (int k = 0; k < 3; ++k) h.iface.push_back(h.tets[4 * e + kTetFace[f][k]]);
+    }
+  }
+  // ---- vertex classes (strong coupling, §2.2 eqs. (6)-(7))
+  std::vector<uint8_t> touch(V, 0);  // bit0 fluid, bit1 wall, bit2 interface triangle
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < 4; ++k) touch[h.tets[4 * e + k]] |= (h.dom[e] == 0) ? 1 : 2;
+  for (int32_t v : h.iface) touch[v] |= 4;
+  h.vkind.resize(V);
+  for (int v = 0; v < V; ++v) {
+    uint8_t t = touch[v];
+    if ((t & 3) == 0) return "a vertex belongs to no element";
+    if (t & 4) h.vkind[v] = VK_IFACE;
+    else if ((t & 3) == 3) return "a vertex touches fluid and wall elements but no interface triangle";
+    else h.vkind[v] = (t & 1) ? VK_FLUID : VK_SOLID;
+  }
+  // ---- row classes and Dirichlet rows (§2.1 eqs. (1)-(3))
+  const size_t n = 7 * (size_t)V;
+  h.rowkind_base.assign(n, RK_ELEM);
+  h.forced_zero.assign(n, 0);
+  std::vector<uint8_t> bc(V, 0);  // bit0 inlet, bit1 outlet, bit2 ring
+  for (int b = 0; b < h.B; ++b) {
+    int tag = h.btag[b];
+    uint8_t bit = tag == FSI_TAG_FLUID_INLET ? 1 : tag == FSI_TAG_FLUID_OUTLET ? 2
+                  : (tag == FSI_TAG_SOLID_RING_IN || tag == FSI_TAG_SOLID_RING_OUT) ? 4 : 0;
+    for (int k = 0; k < 3; ++k) bc[h.bfaces[3 * b + k]] |= bit;
+  }
+  for (int v = 0; v < V; ++v) {
+    uint8_t* rk = &h.rowkind_base[7 * (size_t)v];
+    if (h.vkind[v] != VK_FLUID) rk[4] = rk[5] = rk[6] = RK_KIN;
+    if (h.vkind[v] == VK_SOLID) rk[3] = RK_DUMMY;
+    static const int uvd[6] = {0, 1, 2, 4, 5, 6};
+    if (bc[v] & 4) {
+      for (int c : uvd) { rk[c] = RK_DIR; h.forced_zero[7 * (size_t)v + c] = 1; }
+    } else if (bc[v] & 1) {
+      for (int c : uvd) rk[c] = RK_DIR;
+    } else if (bc[v] & 2) {
+      rk[4] = rk[5] = rk[6] = RK_DIR;
+    }
+  }
+  // ---- block pattern: unique sorted (row, col) pairs of vertices sharing an element
+  std::vector<int64_t> pairs;
+  pairs.reserve((size_t)E * 16 + V);
+  for (int v = 0; v < V; ++v) pairs.push_back((int64_t)v * V + v);
+  for (int e = 0; e < E; ++e)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) pairs.push_back((int64_t)h.tets[4 * e + i] * V + h.tets[4 * e + j]);
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  h.rowptr.assign(V + 1, 0);
+  h.colind.resize(pairs.size());
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    h.rowptr[pairs[k] / V + 1]++;
+    h.colind[k] = (int32_t)(pairs[k] % V);
+  }
+  for (int v = 0; v < V; ++v) h.rowptr[v + 1] += h.rowptr[v];
+  // ---- element lists and gather maps (ascending element order in every list)
+  h.fluid_elems.clear();
+  h.solid_elems.clear();
+  for (int e = 0; e < E; ++e) (h.dom[e] == 0 ? h.fluid_elems : h.solid_elems).push_back(e);
+  h.vinc_ptr.assign(V + 1, 0);
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < 4; ++k) h.vinc_ptr[h.tets[4 * e + k] + 1]++;
+  for (int v = 0; v < V; ++v) h.vinc_ptr[v + 1] += h.vinc_ptr[v];
+  h.vinc.resize((size_t)E * 4);
+  {
+    std::vector<int32_t> fill(h.vinc_ptr.begin(), h.vinc_ptr.end() - 1);
+    for (int e = 0; e < E; ++e)
+      for (int k = 0; k < 4; ++k) h.vinc[fill[h.tets[4 * e + k]]++] = e * 4 + k;
+  }
+  const int64_t nnzb = (int64_t)h.colind.size();
+  std::vector<int32_t> blk((size_t)E * 16);
+  for (int e = 0; e < E; ++e)
+    for (int a = 0; a < 4; ++a) {
+      int va = h.tets[4 * e + a];
+      const int32_t* c0 = &h.colind[h.rowptr[va]];
+      const int32_t* c1 = &h.colind[h.rowptr[va + 1]];
+      for (int b = 0; b < 4; ++b) {
+        const int32_t* p = std::lower_bound(c0, c1, h.tets[4 * e + b]);
+        blk[16 * (size_t)e + 4 * a + b] = (int32_t)(p - h.colind.data());
+      }
+    }
+  h.bctr_ptr.assign(nnzb + 1, 0);
+  for (size_t i = 0; i < blk.size(); ++i) h.bctr_ptr[blk[i] + 1]++;
+  for (int64_t k = 0; k < nnzb; ++k) h.bctr_ptr[k + 1] += h.bctr_ptr[k];
+  h.bctr.resize(blk.size());
+  {
+    std::vector<int32_t> fill(h.bctr_ptr.begin(), h.bctr_ptr.end() - 1);
+    for (size_t i = 0; i < blk.size(); ++i) h.bctr[fill[blk[i]]++] = (int32_t)i;  // i = e*16+a*4+b
+  }
+  return "";
+}
+
+// ---------------------------------------------------------------------------------------
+// Partition: recursive coordinate bisection.  A set of vertices is cut along the longest
+// side of its bounding box (first axis on ties); the first floor(|S| nl / np) vertices
+// in (coordinate, id) order go to the lower nl = np/2 parts.
+// ---------------------------------------------------------------------------------------
+static void rcb(const HostSetup& h, std::vector<int32_t>& ids, size_t lo, size_t hi, int p0, int np,
+                std::vector<int32_t>& part) {
+  if (np == 1) {
+    for (size_t i = lo; i < hi; ++i) part[ids[i]] = p0;
+    return;
+  }
+  double mn[3], mx[3];
+  for (int k = 0; k < 3; ++k) { mn[k] = 1e300; mx[k] = -1e300; }
+  for (size_t i = lo; i < hi; ++i)
+    for (int k = 0; k < 3; ++k) {
+      double x = h.X[3 * (size_t)ids[i] + k];
+      if (x < mn[k]) mn[k] = x;
+      if (x > mx[k]) mx[k] = x;
+    }
+  int ax = 0;
+  if (mx[1] - mn[1] > mx[ax] - mn[ax]) ax = 1;
+  if (mx[2] - mn[2] > mx[ax] - mn[ax]) ax = 2;
+  const int nl = np / 2;
+  const size_t cut = lo + (size_t)(((int64_t)(hi - lo) * nl) / np);
+  auto key_less = [&](int32_t a, int32_t b) {
+    double xa = h.X[3 * (size_t)a + ax], xb = h.X[3 * (size_t)b + ax];
+    return xa < xb || (xa == xb && a < b);
+  };
+  if (cut > lo && cut < hi) std::nth_element(ids.begin() + lo, ids.begin() + cut, ids.begin() + hi, key_less);
+  rcb(h, ids, lo, cut, p0, nl, part);
+  rcb(h, ids, cut, hi, p0 + nl, np - nl, part);
+}
+
+// ---------------------------------------------------------------------------------------
+// Reverse Cuthill-McKee on an induced subgraph (§4.5).  Vertices compare by (degree in
+// the subgraph, global id).  Each connected piece starts from the smallest unvisited
+// vertex, moved to a pseudo-peripheral vertex by the George-Liu search (repeat: take the
+// smallest vertex of the deepest BFS level; keep it while its level structure is deeper).
+// ---------------------------------------------------------------------------------------
+struct SubGraph {
+  const HostSetup* h;
+  std::vector<int32_t> deg;     // by global id; -1 = not in the set
+  bool has(int v) const { return deg[v] >= 0; }
+  bool before(int a, int b) const { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; }
+};
+
+// BFS depth (number of levels) from r and the smallest vertex of its last level.
+static int bfs_depth(const SubGraph& G, int r, std::vector<int32_t>& stamp, int tag, int* last_min) {
+  const HostSetup& h = *G.h;
+  std::vector<int32_t> cur(1, r), nxt;
+  stamp[r] = tag;
+  int depth = 0;
+  int best = r;
+  while (!cur.empty()) {
+    ++depth;
+    best = cur[0];
+    for (int v : cur)
+      if (G.before(v, best)) best = v;
+    nxt.clear();
+    for (int v : cur)
+      for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+        int u = h.colind[k];
+        if (u != v && G.has(u) && stamp[u] != tag) { stamp[u] = tag; nxt.push_back(u); }
+      }
+    cur.swap(nxt);
+  }
+  *last_min = best;
+  return depth;
+}
+
+static void rcm(const HostSetup& h, const std::vector<int32_t>& set, std::vector<int32_t>& out) {
+  SubGraph G;
+  G.h = &h;
+  G.deg.assign(h.V, -1);
+  for (int v : set) G.deg[v] = 0;
+  for (int v : set)
+    for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+      int u = h.colind[k];
+      if (u != v && G.has(u)) G.deg[v]++;
+    }
+  std::vector<int32_t> stamp(h.V, -1);
+  std::vector<uint8_t> done(h.V, 0);
+  int tag = 0;
+  std::vector<int32_t> seq;
+  seq.reserve(set.size());
+  std::vector<int32_t> sorted_set(set);
+  std::sort(sorted_set.begin(), sorted_set.end(), [&](int a, int b) { return G.before(a, b); });
+  size_t scan = 0;
+  while (seq.size() < set.size()) {
+    while (done[sorted_set[scan]]) ++scan;
+    int r = sorted_set[scan];
+    int cand;
+    int dr = bfs_depth(G, r, stamp, ++tag, &cand);
+    for (;;) {
+      int cand2;
+      int dc = bfs_depth(G, cand, stamp, ++tag, &cand2);
+      if (dc > dr) { r = cand; dr = dc; cand = cand2; }
+      else break;
+    }
+    size_t head = seq.size();
+    seq.push_back(r);
+    done[r] = 1;
+    std::vector<int32_t> nb;
+    while (head < seq.size()) {
+      int v = seq[head++];
+      nb.clear();
+      for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+        int u = h.colind[k];
+        if (u != v && G.has(u) && !done[u]) nb.push_back(u);
+      }
+      std::sort(nb.begin(), nb.end(), [&](int a, int b) { return G.before(a, b); });
+      for (int u : nb) { done[u] = 1; seq.push_back(u); }
+    }
+  }
+  out.assign(seq.rbegin(), seq.rend());
+}
+
+std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
+  const int V = h.V, ns = o.nsub;
+  h.ns = ns;
+  if (o.part) {
+    h.part.assign(o.part, o.part + V);
+    for (int v = 0; v < V; ++v)
+      if (h.part[v] < 0 || h.part[v] >= ns) return "partition entry out of range";
+  } else {
+    h.part.assign(V, 0);
+    std::vector<int32_t> ids(V);
+    std::iota(ids.begin(), ids.end(), 0);
+    rcb(h, ids, 0, V, 0, ns, h.part);
+  }
+  h.sub_row_off.assign(ns + 1, 0);
+  h.sub_nowned.assign(ns, 0);
+  h.lglob.clear();
+  h.lowned.clear();
+  h.lrowptr.assign(1, 0);
+  h.lcol.clear();
+  h.lsrc.clear();
+  h.ldiag.clear();
+  h.fwd_sub_lvl.assign(1, 0);
+  h.fwd_lvl_ptr.assign(1, 0);
+  h.fwd_rows.clear();
+  h.bwd_sub_lvl.assign(1, 0);
+  h.bwd_lvl_ptr.assign(1, 0);
+  h.bwd_rows.clear();
+  h.kent_ptr.assign(1, 0);
+  h.kent_ik.clear();
+  h.kent_dk.clear();
+  h.kent_tptr.assign(1, 0);
+  h.tri_kj.clear();
+  h.tri_ij.clear();
+
+  std::vector<int32_t> owners_of(V);
+  std::vector<std::vector<int32_t>> members(ns);
+  for (int v = 0; v < V; ++v) members[h.part[v]].push_back(v);
+  std::vector<int32_t> mark(V, -1), loc(V, -1);
+  const int L = o.ilu_level;
+  for (int s = 0; s < ns; ++s) {
+    // extended set: delta rings of vertex-graph neighbours around the owned vertices
+    std::vector<int32_t> set = members[s];
+    for (int v : set) mark[v] = s;
+    size_t ring_begin = 0;
+    for (int d = 0; d < o.overlap; ++d) {
+      size_t ring_end = set.size();
+      for (size_t i = ring_begin; i < ring_end; ++i) {
+        int v = set[i];
+        for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+          int u = h.colind[k];
+          if (mark[u] != s) { mark[u] = s; set.push_back(u); }
+        }
+      }
+      ring_begin = ring_end;
+    }
+    std::vector<int32_t> order;
+    rcm(h, set, order);
+    const int m = (int)order.size();
+    const int base = (int)h.lglob.size();
+    for (int l = 0; l < m; ++l) loc[order[l]] = l;
+    for (int l = 0; l < m; ++l) {
+      h.lglob.push_back(order[l]);
+      uint8_t own = h.part[order[l]] == s;
+      h.lowned.push_back(own);
+      h.sub_nowned[s] += own;
+    }
+    // ILU(l) pattern by levels of fill: row by row, pivots in ascending order through a
+    // min-heap; lev(i,j) = min over pivots k of lev(i,k) + lev(k,j) + 1, kept if <= l.
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> rowpat(m);  // (col, level), sorted
+    std::vector<int32_t> lev(m, INT_MAX);
+    std::vector<int32_t> srcb(m, -1);
+    for (int i = 0; i < m; ++i) {
+      int g = order[i];
+      std::vector<int32_t> cols;
+      std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
+      for (int k = h.rowptr[g]; k < h.rowptr[g + 1]; ++k) {
+        int u = h.colind[k];
+        if (mark[u] != s) continue;
+        int c = loc[u];
+        lev[c] = 0;
+        srcb[c] = k;
+        cols.push_back(c);
+        if (c < i) heap.push(c);
+      }
+      int last = -1;
+      while (L > 0 && !heap.empty()) {
+        int k = heap.top();
+        heap.pop();
+        if (k == last) continue;
+        last = k;
+        for (const auto& kj : rowpat[k]) {
+          if (kj.first <= k) continue;
+          int nl = lev[k] + kj.second + 1;
+          if (nl > L) continue;
+          int j = kj.first;
+          if (lev[j] == INT_MAX) {
+            lev[j] = nl;
+            cols.push_back(j);
+            if (j < i) heap.push(j);
+          } else if (nl < lev[j]) {
+            lev[j] = nl;
+          }
+        }
+      }
+      std::sort(cols.begin(), cols.end());
+      for (int c : cols) {
+        rowpat[i].push_back({c, lev[c]});
+        if (c == i) h.ldiag.push_back((int32_t)h.lcol.size());
+        h.lcol.push_back(base + c);
+        h.lsrc.push_back(srcb[c]);
+      }
+      for (int c : cols) { lev[c] = INT_MAX; srcb[c] = -1; }
+      h.lrowptr.push_back((int32_t)h.lcol.size());
+      if ((int)h.ldiag.size() != base + i + 1) return "missing diagonal block";
+    }
+    for (int l = 0; l < m; ++l) loc[order[l]] = -1;
+    // level schedules of the two triangular sweeps
+    auto rowb = [&](int i) { return h.lrowptr[base + i]; };
+    auto rowe = [&](int i) { return h.lrowptr[base + i + 1]; };
+    std::vector<int32_t> lf(m, 0), lb(m, 0);
+    int nf = 0, nbk = 0;
+    for (int i = 0; i < m; ++i) {
+      int lv = 0;
+      for (int p = rowb(i); p < h.ldiag[base + i]; ++p) lv = std::max(lv, lf[h.lcol[p] - base] + 1);
+      lf[i] = lv;
+      nf = std::max(nf, lv + 1);
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      int lv = 0;
+      for (int p = h.ldiag[base + i] + 1; p < rowe(i); ++p) lv = std::max(lv, lb[h.lcol[p] - base] + 1);
+      lb[i] = lv;
+      nbk = std::max(nbk, lv + 1);
+    }
+    auto emit = [&](const std::vector<int32_t>& lv, int nlev, std::vector<int32_t>& lvl_ptr,
+                    std::vector<int32_t>& rows, std::vector<int32_t>& sub_lvl) {
+      std::vector<int32_t> cnt(nlev + 1, 0);
+      for (int i = 0; i < m; ++i) cnt[lv[i] + 1]++;
+      for (int l = 0; l < nlev; ++l) cnt[l + 1] += cnt[l];
+      size_t r0 = rows.size();
+      rows.resize(r0 + m);
+      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int i = 0; i < m; ++i) rows[r0 + fill[lv[i]]++] = base + i;
+      for (int l = 0; l < nlev; ++l) lvl_ptr.push_back((int32_t)(r0 + cnt[l + 1]));
+      sub_lvl.push_back((int32_t)lvl_ptr.size() - 1);
+    };
+    emit(lf, nf, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl);
+    emit(lb, nbk, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl);
+    // factorization work lists: for each row i, its L blocks (ascending k) with the
+    // position of D_k and the pairs (U_kj, A_ij) for j > k present in row i
+    for (int i = 0; i < m; ++i) {
+      const int32_t* ci0 = &h.lcol[rowb(i)];
+      const int32_t* ci1 = &h.lcol[0] + rowe(i);
+      for (int p = rowb(i); p < h.ldiag[base + i]; ++p) {
+        int k = h.lcol[p] - base;
+        h.kent_ik.push_back(p);
+        h.kent_dk.push_back(h.ldiag[base + k]);
+        for (int q = h.ldiag[base + k] + 1; q < rowe(k); ++q) {
+          const int32_t* f = std::lower_bound(ci0, ci1, h.lcol[q]);
+          if (f != ci1 && *f == h.lcol[q]) {
+            h.tri_kj.push_back(q);
+            h.tri_ij.push_back((int32_t)(f - &h.lcol[0]));
+          }
+        }
+        h.kent_tptr.push_back((int32_t)h.tri_kj.size());
+      }
+      h.kent_ptr.push_back((int32_t)h.kent_ik.size());
+    }
+    h.sub_row_off[s + 1] = (int32_t)h.lglob.size();
+  }
+  (void)owners_of;
+  return "";
+}
+
+}  // namespace fsi

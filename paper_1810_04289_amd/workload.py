@@ -31,6 +31,10 @@ TAG_WALL_OUTER = 5
 FLUID = 0
 SOLID = 1
 
+# Lattice spacing (cm) of the tree workloads: depth 3 gives about 203k vertices and
+# 1.37M active unknowns; depth 1 (about 26k vertices) is the small sampled variant.
+TREE_H = {1: 0.08, 3: 0.049}
+
 # Faces of a positively oriented tet (v0..v3), each listed with outward orientation.
 _TET_FACES = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]], dtype=np.int64)
 
