@@ -363,6 +363,11 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->nnzb = (int64_t)h.colind.size();
   s->R = (int64_t)h.lglob.size();
   s->NB = (int64_t)h.lcol.size();
+  for (int64_t i = 0; i < s->R; ++i) {
+    s->max_lblk = std::max(s->max_lblk, h.ldiag[i] - h.lrowptr[i]);
+    s->max_ublk = std::max(s->max_ublk, h.lrowptr[i + 1] - h.ldiag[i] - 1);
+    s->max_rowblk = std::max(s->max_rowblk, h.lrowptr[i + 1] - h.lrowptr[i]);
+  }
   std::vector<int32_t> blkrow(s->nnzb);
   for (int v = 0; v < h.V; ++v)
     for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) blkrow[k] = v;
@@ -397,6 +402,40 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->bwd_sub_lvl = upload(s, h.bwd_sub_lvl);
   s->bwd_lvl_ptr = upload(s, h.bwd_lvl_ptr);
   s->bwd_rows = upload(s, h.bwd_rows);
+  {
+    // per-wavefront task lists of both sweeps (level order inside each wavefront)
+    auto tasks = [&](bool bwd, const std::vector<int32_t>& sub_lvl, const std::vector<int32_t>& lvl_ptr,
+                     const std::vector<int32_t>& rows, const std::vector<int32_t>& qslot, int32_t** wtask_d,
+                     int4** task_d, int2** aux_d) {
+      std::vector<int32_t> wtask(h.ns * kSweepWaves + 1, 0);
+      std::vector<int4> task;
+      std::vector<int2> aux;
+      task.reserve(rows.size());
+      aux.reserve(rows.size());
+      for (int sd = 0; sd < h.ns; ++sd)
+        for (int w = 0; w < kSweepWaves; ++w) {
+          for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L)
+            for (int q = lvl_ptr[L] + w; q < lvl_ptr[L + 1]; q += kSweepWaves) {
+              const int i = rows[q];
+              const int g = h.lglob[i] | (h.lowned[i] ? (int)0x80000000u : 0);
+              task.push_back(bwd ? make_int4(i, g, h.ldiag[i], h.lrowptr[i + 1])
+                                 : make_int4(i, g, h.lrowptr[i], h.ldiag[i]));
+              aux.push_back(make_int2(qslot[q], L - sub_lvl[sd]));
+            }
+          wtask[sd * kSweepWaves + w + 1] = (int32_t)task.size();
+        }
+      *wtask_d = upload(s, wtask);
+      *task_d = upload(s, task);
+      *aux_d = upload(s, aux);
+    };
+    tasks(false, h.fwd_sub_lvl, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_qslot, &s->fwd_wtask, &s->fwd_task,
+          &s->fwd_task_aux);
+    tasks(true, h.bwd_sub_lvl, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, &s->bwd_wtask, &s->bwd_task,
+          &s->bwd_task_aux);
+    std::vector<int32_t> lbyte(h.lslot.size());
+    for (size_t p = 0; p < lbyte.size(); ++p) lbyte[p] = h.lslot[p] >= 0 ? 56 * h.lslot[p] : 0;
+    s->lslot = upload(s, lbyte);
+  }
   s->kent_ptr = upload(s, h.kent_ptr);
   s->kent_ik = upload(s, h.kent_ik);
   s->kent_dk = upload(s, h.kent_dk);

@@ -17,6 +17,7 @@ enum : uint8_t { RK_ELEM = 0, RK_DIR = 1, RK_KIN = 2, RK_DUMMY = 3 };
 
 constexpr int kMaxRestart = 200;
 constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic sums
+constexpr int kSweepWaves = 8;    // wavefronts per subdomain in the triangular sweeps
 
 // Host-side setup products (independent of any device state).
 struct HostSetup {
@@ -55,6 +56,11 @@ struct HostSetup {
   std::vector<int32_t> kent_ptr;       // [R+1]
   std::vector<int32_t> kent_ik, kent_dk, kent_tptr;  // [K], [K], [K+1]
   std::vector<int32_t> tri_kj, tri_ij;               // [T]
+  // LDS slots of the sweeps: a row's result occupies a slot from its level to the level
+  // of its last reader (interval colouring per subdomain and direction).
+  std::vector<int32_t> fwd_qslot, bwd_qslot;  // per schedule slot: own LDS slot or -1 (no reader)
+  std::vector<int32_t> lslot;                 // per block: LDS slot of the column row (L: fwd, U: bwd)
+  int nslots = 0;                             // max slots over subdomains and directions
 };
 
 std::string build_topology(HostSetup& h);
@@ -74,6 +80,7 @@ struct fsi_solver {
   hipStream_t stream = nullptr;
   std::string err;
   int64_t n = 0, nnzb = 0, R = 0, NB = 0;
+  int max_lblk = 0, max_ublk = 0, max_rowblk = 0;  // longest L part, U part, whole local row
 
   // mesh and maps
   double* X = nullptr;
@@ -93,6 +100,15 @@ struct fsi_solver {
   uint8_t* lowned = nullptr;
   int32_t *fwd_sub_lvl = nullptr, *fwd_lvl_ptr = nullptr, *fwd_rows = nullptr;
   int32_t *bwd_sub_lvl = nullptr, *bwd_lvl_ptr = nullptr, *bwd_rows = nullptr;
+  // sweep task lists: the rows of a subdomain's level go to its kSweepWaves wavefronts
+  // round-robin; wavefront w of subdomain s takes tasks [wtask[s*kSweepWaves + w],
+  // wtask[s*kSweepWaves + w + 1]) in level order.  task = {row, global vertex (bit 31 =
+  // owned), first, last} (forward: L blocks [first, last); backward: D at first, U blocks
+  // (first, last)); task_aux = {own LDS slot or -1, level within the subdomain}.
+  int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr;
+  int4 *fwd_task = nullptr, *bwd_task = nullptr;
+  int2 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
+  int32_t* lslot = nullptr;  // per block: LDS byte offset (56 * slot) of its column row's slot
   int32_t *kent_ptr = nullptr, *kent_ik = nullptr, *kent_dk = nullptr, *kent_tptr = nullptr;
   int32_t *tri_kj = nullptr, *tri_ij = nullptr;
   int32_t* sub_row_off = nullptr;

@@ -15,9 +15,12 @@
 //   factor: one wavefront per row, lane (r,c) < 49 owns entry (r,c) of every block of the
 //           row; the 7x7 products take a block row from lane registers by shuffles;
 //           the pivot block is inverted by Gauss-Jordan with partial pivoting across lanes.
-//   sweeps: one wavefront per row, eight block slots per component; the forward sweep
-//           gathers R_i^delta v on the fly, the backward sweep applies D_i through shuffles
-//           and writes owned rows straight into z (restricted prolongation).
+//   sweeps: one wavefront per row, lane (r,c) < 56 owns entry (r,c) of each block of the
+//           row (coalesced block loads); results of earlier levels come from LDS slots; the
+//           forward sweep gathers R_i^delta v on the fly, the backward sweep applies D_i and
+//           writes owned rows straight into z (restricted prolongation).
+#include <algorithm>
+
 #include "fsi_internal.hpp"
 
 namespace fsi {
@@ -34,76 +37,155 @@ __global__ void __launch_bounds__(256) k_ilu_gather(int64_t nb, const int32_t* _
   fac[gid] = src >= 0 ? vals[49 * (size_t)src + e] : 0.0;
 }
 
-__global__ void __launch_bounds__(1024) k_ilu_factor(const int32_t* __restrict__ sub_lvl,
-                                                     const int32_t* __restrict__ lvl_ptr,
-                                                     const int32_t* __restrict__ rows,
-                                                     const int32_t* __restrict__ kent_ptr,
-                                                     const int32_t* __restrict__ kent_ik,
-                                                     const int32_t* __restrict__ kent_dk,
-                                                     const int32_t* __restrict__ kent_tptr,
-                                                     const int32_t* __restrict__ tri_kj,
-                                                     const int32_t* __restrict__ tri_ij,
-                                                     const int32_t* __restrict__ ldiag, double* __restrict__ fac,
-                                                     double* __restrict__ udiag, int32_t* __restrict__ flags) {
+constexpr int kTri = 8;  // update pairs in flight per wavefront
+
+// Wavefront-scope ordering of LDS accesses between lanes of one wavefront (LDS operations
+// of a wavefront are processed in order; the fences keep the compiler from reordering).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Factorization of one subdomain per workgroup, one row per wavefront.  The row being
+// factored is staged in the wavefront's LDS slice (maxrow blocks), so every access to it
+// during the pivot loop is an LDS access; pivot rows k (final) and D_k are read from
+// memory.  The row's pivot list is read once (one lane per pivot) and broadcast with
+// readlane; while pivot e is applied, pivot e+1's D_k column, its (U_kj, A_ij) index
+// pairs and its first kTri U_kj columns are already in flight.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ sub_lvl,
+                                                   const int32_t* __restrict__ lvl_ptr,
+                                                   const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ lrowptr,
+                                                   const int32_t* __restrict__ kent_ptr,
+                                                   const int32_t* __restrict__ kent_ik,
+                                                   const int32_t* __restrict__ kent_dk,
+                                                   const int32_t* __restrict__ kent_tptr,
+                                                   const int32_t* __restrict__ tri_kj,
+                                                   const int32_t* __restrict__ tri_ij,
+                                                   const int32_t* __restrict__ ldiag, double* __restrict__ fac,
+                                                   double* __restrict__ udiag, int32_t* __restrict__ flags,
+                                                   int maxrow) {
+  extern __shared__ double lds[];
+  constexpr int NW = NT / 64;
   const int s = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ent = lane < 49 ? lane : 48;  // lanes 49..63 shadow entry 48 and never store
   const bool owner = lane < 49;
   const int rr = ent / 7, cc = ent % 7;
-  for (int L = sub_lvl[s]; L < sub_lvl[s + 1]; ++L) {
+  double* row = lds + (size_t)wave * maxrow * 49;
+  const int L0 = sub_lvl[s], L1 = sub_lvl[s + 1];
+  for (int L = L0; L < L1; ++L) {
     const int r1 = lvl_ptr[L + 1];
-    for (int q = lvl_ptr[L] + wave; q < r1; q += nwaves) {
+    for (int q = lvl_ptr[L] + wave; q < r1; q += NW) {
       const int i = rows[q];
-      for (int ke = kent_ptr[i]; ke < kent_ptr[i + 1]; ++ke) {
-        const size_t pik = (size_t)kent_ik[ke] * 49, pdk = (size_t)kent_dk[ke] * 49;
-        const double a = fac[pik + ent];
-        double arow[7];
+      const int rb = lrowptr[i], nbe = (lrowptr[i + 1] - rb) * 49;
+      const size_t gb = (size_t)rb * 49;
+      // stage the row: all loads of a round issued before its LDS writes
+      for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+        double tmp[8];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) arow[m] = __shfl(a, rr * 7 + m, 64);
-        double l = 0.0;
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + lane + 64 * u;
+          tmp[u] = fac[gb + (e < nbe ? e : nbe - 1)];
+        }
 #pragma unroll
-        for (int m = 0; m < 7; ++m) l += arow[m] * fac[pdk + 7 * m + cc];   // L_ik = A_ik D_k
-        if (owner) fac[pik + ent] = l;
-        double lrow[7];
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e < nbe) row[e] = tmp[u];
+        }
+      }
+      wave_lds_sync();
+      const int kb = kent_ptr[i], nk = kent_ptr[i + 1] - kb;
+      for (int kbase = 0; kbase < nk; kbase += 64) {
+        const int lk = kb + kbase + lane;
+        const bool hk = kbase + lane < nk;
+        const int mik = hk ? kent_ik[lk] - rb : 0, mdk = hk ? kent_dk[lk] : 0;
+        const int mt0 = hk ? kent_tptr[lk] : 0, mt1 = hk ? kent_tptr[lk + 1] : 0;
+        const int cnt = nk - kbase < 64 ? nk - kbase : 64;
+        // prefetch of pivot e: D_k column, pair indices (lane-indexed), first kTri U_kj columns
+        auto prefetch = [&](int e, double d[7], int& ikj, int& iij, double b[kTri][7]) {
+          const size_t pdk = (size_t)__builtin_amdgcn_readlane(mdk, e) * 49;
+          const int tb = __builtin_amdgcn_readlane(mt0, e), te = __builtin_amdgcn_readlane(mt1, e);
 #pragma unroll
-        for (int m = 0; m < 7; ++m) lrow[m] = __shfl(l, rr * 7 + m, 64);
-        // A_ij -= L_ik U_kj for the (U_kj, A_ij) pairs of this pivot, four pairs in
-        // flight at a time (the U_kj rows are final; the A_ij blocks are distinct)
-        int t = kent_tptr[ke];
-        const int te = kent_tptr[ke + 1];
-        for (; t + 4 <= te; t += 4) {
-          size_t pkj[4], pij[4];
+          for (int m = 0; m < 7; ++m) d[m] = fac[pdk + 7 * m + cc];
+          const int lt = tb + lane < te ? tb + lane : (te > tb ? tb : 0);  // no pairs: any valid index
+          ikj = tri_kj[lt];
+          iij = tri_ij[lt] - rb;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            pkj[u] = (size_t)tri_kj[t + u] * 49;
-            pij[u] = (size_t)tri_ij[t + u] * 49;
+          for (int u = 0; u < kTri; ++u) {
+            const int src = u < te - tb ? u : 0;
+            const size_t pkj = (size_t)__builtin_amdgcn_readlane(ikj, src) * 49;
+#pragma unroll
+            for (int m = 0; m < 7; ++m) b[u][m] = fac[pkj + 7 * m + cc];
           }
-          double bk[4][7], cur[4];
+        };
+        double dk[7], b0[kTri][7];
+        int ikj, iij;
+        prefetch(0, dk, ikj, iij, b0);
+        for (int e = 0; e < cnt; ++e) {
+          const int pik = __builtin_amdgcn_readlane(mik, e) * 49;
+          const int tb = __builtin_amdgcn_readlane(mt0, e), te = __builtin_amdgcn_readlane(mt1, e);
+          const int nt = te - tb;
+          double arow[7];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int m = 0; m < 7; ++m) arow[m] = row[pik + 7 * rr + m];
+          double l = 0.0;
 #pragma unroll
-            for (int m = 0; m < 7; ++m) bk[u][m] = fac[pkj[u] + 7 * m + cc];
-            cur[u] = fac[pij[u] + ent];
-          }
+          for (int m = 0; m < 7; ++m) l += arow[m] * dk[m];                    // L_ik = A_ik D_k
+          wave_lds_sync();
+          if (owner) row[pik + ent] = l;
+          wave_lds_sync();
+          double lrow[7];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int m = 0; m < 7; ++m) lrow[m] = row[pik + 7 * rr + m];
+          double dn[7], bn[kTri][7];
+          int nkj = 0, nij = 0;
+          if (e + 1 < cnt) prefetch(e + 1, dn, nkj, nij, bn);
+#pragma unroll
+          for (int u = 0; u < kTri; ++u) {                                         // A_ij -= L_ik U_kj
             double upd = 0.0;
 #pragma unroll
-            for (int m = 0; m < 7; ++m) upd += lrow[m] * bk[u][m];
-            if (owner) fac[pij[u] + ent] = cur[u] - upd;
+            for (int m = 0; m < 7; ++m) upd += lrow[m] * b0[u][m];
+            const int pij = __builtin_amdgcn_readlane(iij, u < nt ? u : 0) * 49;
+            if (owner && u < nt) row[pij + ent] -= upd;
           }
-        }
-        for (; t < te; ++t) {
-          const size_t pkj = (size_t)tri_kj[t] * 49, pij = (size_t)tri_ij[t] * 49;
-          double u = 0.0;
+          for (int t0 = kTri; t0 < nt; t0 += kTri) {   // remaining pairs of this pivot
 #pragma unroll
-          for (int m = 0; m < 7; ++m) u += lrow[m] * fac[pkj + 7 * m + cc];  // A_ij -= L_ik U_kj
-          if (owner) fac[pij + ent] -= u;
+            for (int u = 0; u < kTri; ++u) {
+              const int t = t0 + u < nt ? t0 + u : t0;
+              const size_t pkj = (size_t)(t < 64 ? __builtin_amdgcn_readlane(ikj, t) : tri_kj[tb + t]) * 49;
+#pragma unroll
+              for (int m = 0; m < 7; ++m) b0[u][m] = fac[pkj + 7 * m + cc];
+            }
+#pragma unroll
+            for (int u = 0; u < kTri; ++u) {
+              const int t = t0 + u < nt ? t0 + u : t0;
+              double upd = 0.0;
+#pragma unroll
+              for (int m = 0; m < 7; ++m) upd += lrow[m] * b0[u][m];
+              const int pij = (t < 64 ? __builtin_amdgcn_readlane(iij, t) : tri_ij[tb + t] - rb) * 49;
+              if (owner && t0 + u < nt) row[pij + ent] -= upd;
+            }
+          }
+          wave_lds_sync();
+          if (e + 1 < cnt) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) dk[m] = dn[m];
+#pragma unroll
+            for (int u = 0; u < kTri; ++u)
+#pragma unroll
+              for (int m = 0; m < 7; ++m) b0[u][m] = bn[u][m];
+            ikj = nkj;
+            iij = nij;
+          }
         }
       }
       // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
-      const size_t pii = (size_t)ldiag[i] * 49;
-      double M = fac[pii + ent];
+      const int pd = (ldiag[i] - rb) * 49;
+      double M = row[pd + ent];
       if (owner) udiag[49 * (size_t)i + ent] = M;
       double Iv = (rr == cc) ? 1.0 : 0.0;
       bool bad = false;
@@ -126,79 +208,21 @@ __global__ void __launch_bounds__(1024) k_ilu_factor(const int32_t* __restrict__
         if (rr != p) { M = M - fct * Mp; Iv = Iv - fct * Ip; }
       }
       if (bad && lane == 0) atomicOr(&flags[1], 1);
-      if (owner) fac[pii + ent] = Iv;
-    }
-    __syncthreads();
-  }
-}
-
-// Sweeps: one wavefront per row.  Lane = 8*r + slot: component r (0..6, r = 7 idle) of
-// the row, block slot 0..7; slot t accumulates blocks t, t+8, t+16, ... of the row so
-// up to eight blocks are in flight per component, then an xor-shuffle tree sums the
-// slots.
-__global__ void __launch_bounds__(512) k_ilu_fwd(const int32_t* __restrict__ sub_lvl, const int32_t* __restrict__ lvl_ptr,
-                                                 const int32_t* __restrict__ rows, const int32_t* __restrict__ lrowptr,
-                                                 const int32_t* __restrict__ ldiag, const int32_t* __restrict__ lcol,
-                                                 const int32_t* __restrict__ lglob, const double* __restrict__ fac,
-                                                 const double* __restrict__ v, double* __restrict__ yl) {
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int r = lane >> 3, sl = lane & 7, rr = r < 7 ? r : 6;
-  for (int L = sub_lvl[s]; L < sub_lvl[s + 1]; ++L) {
-    const int q1 = lvl_ptr[L + 1];
-    for (int q = lvl_ptr[L] + wave; q < q1; q += nw) {
-      const int i = rows[q];
-      const int pd = ldiag[i];
-      double acc = 0.0;
-#pragma unroll 2
-      for (int p = lrowptr[i] + sl; p < pd; p += 8) {
-        const double* Lb = fac + 49 * (size_t)p + 7 * rr;
-        const double* yk = yl + 7 * (size_t)lcol[p];
+      wave_lds_sync();
+      if (owner) row[pd + ent] = Iv;
+      wave_lds_sync();
+      for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+        double tmp[8];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) acc += Lb[m] * yk[m];
-      }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
-      if (sl == 0 && r < 7) yl[7 * (size_t)i + r] = v[7 * (size_t)lglob[i] + r] - acc;
-    }
-    __syncthreads();
-  }
-}
-
-__global__ void __launch_bounds__(512) k_ilu_bwd(const int32_t* __restrict__ sub_lvl, const int32_t* __restrict__ lvl_ptr,
-                                                 const int32_t* __restrict__ rows, const int32_t* __restrict__ lrowptr,
-                                                 const int32_t* __restrict__ ldiag, const int32_t* __restrict__ lcol,
-                                                 const int32_t* __restrict__ lglob, const uint8_t* __restrict__ lowned,
-                                                 const double* __restrict__ fac, double* __restrict__ yl,
-                                                 double* __restrict__ z) {
-  const int s = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int r = lane >> 3, sl = lane & 7, rr = r < 7 ? r : 6;
-  for (int L = sub_lvl[s]; L < sub_lvl[s + 1]; ++L) {
-    const int q1 = lvl_ptr[L + 1];
-    for (int q = lvl_ptr[L] + wave; q < q1; q += nw) {
-      const int i = rows[q];
-      const int pd = ldiag[i];
-      double acc = 0.0;
-#pragma unroll 2
-      for (int p = pd + 1 + sl; p < lrowptr[i + 1]; p += 8) {
-        const double* Ub = fac + 49 * (size_t)p + 7 * rr;
-        const double* xj = yl + 7 * (size_t)lcol[p];
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + lane + 64 * u;
+          tmp[u] = row[e < nbe ? e : nbe - 1];
+        }
 #pragma unroll
-        for (int m = 0; m < 7; ++m) acc += Ub[m] * xj[m];
-      }
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
-      const double t = yl[7 * (size_t)i + rr] - acc;   // component rr of y_i - sum U_ij x_j
-      const double* D = fac + 49 * (size_t)pd + 7 * rr;
-      double x = 0.0;
-#pragma unroll
-      for (int c = 0; c < 7; ++c) x += D[c] * __shfl(t, 8 * c, 64);
-      if (sl == 0 && r < 7) {
-        yl[7 * (size_t)i + r] = x;
-        if (lowned[i]) z[7 * (size_t)lglob[i] + r] = x;
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + lane + 64 * u;
+          if (e < nbe) fac[gb + e] = tmp[u];
+        }
       }
     }
     __syncthreads();
@@ -209,22 +233,278 @@ hipError_t launch_pc_setup(fsi_solver* s) {
   if (s->NB == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ilu_gather, dim3(nblk(s->NB * 49, 256)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
                      s->fac);
-  FSI_PROF_LAUNCH(s, "ilu_factor",
-                  hipLaunchKernelGGL(k_ilu_factor, dim3(s->h.ns), dim3(1024), 0, s->stream, s->fwd_sub_lvl,
-                                     s->fwd_lvl_ptr, s->fwd_rows, s->kent_ptr, s->kent_ik, s->kent_dk, s->kent_tptr,
-                                     s->tri_kj, s->tri_ij, s->ldiag, s->fac, s->udiag, s->flags));
+  // up to four row-staging wavefronts per workgroup, as many as the longest row allows
+  const size_t per_wave = (size_t)s->max_rowblk * 49 * sizeof(double);
+  const int waves = (int)std::min<size_t>(4, (160 * 1024) / per_wave);
+  if (waves < 1) return hipErrorInvalidConfiguration;  // a row too long to stage in LDS
+  const size_t lds = per_wave * waves;
+  auto go = [&](auto kern, int nt) -> hipError_t {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    FSI_PROF_LAUNCH(s, "ilu_factor",
+                    hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_sub_lvl, s->fwd_lvl_ptr,
+                                       s->fwd_rows, s->lrowptr, s->kent_ptr, s->kent_ik, s->kent_dk, s->kent_tptr,
+                                       s->tri_kj, s->tri_ij, s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk));
+    return hipSuccess;
+  };
+  hipError_t e = waves >= 4 ? go(k_ilu_factor<256>, 256) : waves == 3 ? go(k_ilu_factor<192>, 192)
+                 : waves == 2 ? go(k_ilu_factor<128>, 128) : go(k_ilu_factor<64>, 64);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
-hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
+// Sweeps: one wavefront per row.  Lane = 8*r + c holds entry (r, c) of a 7x7 block
+// (c = 7 and r = 7 idle), so one load instruction reads a whole 392-byte block
+// contiguously; the row's blocks are multiplied by the column rows' values and summed
+// over blocks per lane, then a DPP tree sums the eight lanes of each row r.
+//
+// Level results travel through LDS: each row whose value is read later in the same sweep
+// owns an LDS slot from its level to its last reader's level (slots assigned on the host
+// by interval colouring; a few hundred slots per subdomain).  The level barrier then only
+// orders LDS traffic, so global loads stay in flight across it.
+//
+// Nothing a wavefront loads from memory depends on values computed in the sweep, so the
+// sweep is a pipeline over the wavefront's task list: the task metadata arrive 64 tasks at
+// a time (one task per lane, broadcast by readlane) and the block values, the column
+// rows' LDS slots and the row's input of task t + D - 1 are requested while task t is
+// computed, into D rotating register sets.  Every task issues the same number of loads
+// (short rows repeat their last block), so the compiler's in-order memory counter waits
+// only for the set about to be used.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over the eight lanes of an aligned group of eight (xor 1, xor 2, then the mirror
+// lane of the other half)
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+struct TaskMeta {  // one task, uniform across the wavefront
+  int row, vtx, first, last, slot, level;
+};
+
+struct TaskChunk {  // lane j: task base + j
+  int4 m;
+  int2 a;
+};
+
+__device__ __forceinline__ TaskChunk load_chunk(const int4* __restrict__ task, const int2* __restrict__ aux, int t,
+                                                int te, int lane) {
+  const int q = t + lane < te ? t + lane : te - 1;
+  return TaskChunk{task[q], aux[q]};
+}
+
+__device__ __forceinline__ TaskMeta chunk_get(const TaskChunk& c, int l) {
+  return TaskMeta{__builtin_amdgcn_readlane(c.m.x, l), __builtin_amdgcn_readlane(c.m.y, l),
+                  __builtin_amdgcn_readlane(c.m.z, l), __builtin_amdgcn_readlane(c.m.w, l),
+                  __builtin_amdgcn_readlane(c.a.x, l), __builtin_amdgcn_readlane(c.a.y, l)};
+}
+
+// Raw buffer loads: a resource spans exactly the bytes a task may read, and the hardware
+// returns 0 for a lane whose offset (vector offset + immediate) falls outside it, without
+// touching memory.  Padding lanes use an offset that is always outside.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+constexpr int kOutside = (int)0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufFlags);
+}
+
+__device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int voff) {
+  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+  return __hiloint2double((int)v.y, (int)v.x);
+}
+
+template <int MB>
+struct TaskData {
+  double A[MB];   // entry (r, c) of the row's first MB blocks; 0 beyond the row and on padding lanes
+  int ls;         // lane b < 64: LDS byte offset of the column row of block b (0 beyond the row)
+  double base;    // forward: v of the vertex (component r); backward: y_i (component r)
+  double D;       // backward: entry (r, c) of D_i (0 on padding lanes)
+};
+
+// voff: 8 * (7r + c) on the 49 block lanes, kOutside on padding lanes
+template <int BWD, int MB>
+__device__ __forceinline__ void task_load(TaskData<MB>& P, const TaskMeta& T, const int32_t* __restrict__ lslot,
+                                          const double* __restrict__ fac, const double* __restrict__ v,
+                                          const double* yl, int lane, int voff, int r) {
+  const int first = BWD ? T.first + 1 : T.first;
+  const int nb = T.last - first;
+  // one resource per group of eight blocks keeps every block offset in the immediate field
+#pragma unroll
+  for (int g = 0; g < MB; g += 8) {
+    const __amdgpu_buffer_rsrc_t ra = span_rsrc(fac + 49 * (size_t)(first + g), nb > g ? 392 * (nb - g) : 0);
+#pragma unroll
+    for (int u = 0; u < 8 && g + u < MB; ++u) P.A[g + u] = span_load_f64(ra, voff + 392 * u);
+  }
+  const __amdgpu_buffer_rsrc_t rl = span_rsrc(lslot + first, 4 * nb);
+  P.ls = (int)__builtin_amdgcn_raw_buffer_load_b32(rl, 4 * lane, 0, 0);
+  const int rv = r < 7 ? r : 6;
+  if (BWD) {
+    P.base = yl[7 * (size_t)T.row + rv];
+    P.D = span_load_f64(span_rsrc(fac + 49 * (size_t)T.first, 392), voff);
+  } else {
+    P.base = v[7 * (size_t)(T.vtx & 0x7fffffff) + rv];
+  }
+}
+
+// ybuf_c: this lane's component column of the LDS slots (byte address of ybuf + 8c)
+template <int BWD, int MB>
+__device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& P, const int32_t* __restrict__ lslot,
+                                         const double* __restrict__ fac, const char* ybuf_c, double* ybuf,
+                                         double* scr, double* yl, double* __restrict__ z, int lane, int e, int r,
+                                         int c) {
+  const int first = BWD ? T.first + 1 : T.first;
+  const int nb = T.last - first;
+  const int cc = c < 7 ? c : 6;
+  double acc = 0.0;
+  // groups of eight blocks: the LDS reads of a group are issued together; blocks beyond
+  // the row contribute A = 0 times a finite slot value
+#pragma unroll
+  for (int g = 0; g < MB; g += 8) {
+    if (g < nb) {
+      double yv[8];
+#pragma unroll
+      for (int u = 0; u < 8 && g + u < MB; ++u)
+        yv[u] = *(const double*)(ybuf_c + __builtin_amdgcn_readlane(P.ls, g + u));
+#pragma unroll
+      for (int u = 0; u < 8 && g + u < MB; ++u) acc = fma(P.A[g + u], yv[u], acc);
+    }
+  }
+  for (int b = MB; b < nb; ++b) {   // blocks beyond the prefetched ones
+    const int off = b < 64 ? __builtin_amdgcn_readlane(P.ls, b) : lslot[first + b];
+    const double a = fac[49 * (size_t)(first + b) + e];
+    const double yv = *(const double*)(ybuf_c + off);
+    acc += (c < 7 && r < 7) ? a * yv : 0.0;
+  }
+  acc = sum8(acc);                  // sum_c of row r of all blocks times the column values
+  double out;
+  if (!BWD) {
+    out = P.base - acc;                                   // y_i = b_i - sum_k L_ik y_k
+    if (c == 0 && r < 7) yl[7 * (size_t)T.row + r] = out;
+  } else {
+    const double t = P.base - acc;                        // y_i - sum_j U_ij x_j
+    if (c == 0 && r < 7) scr[r] = t;
+    wave_lds_sync();
+    const double tc = scr[cc];
+    wave_lds_sync();
+    out = sum8(P.D * tc);                                 // x_i = D_i (...)
+    if (c == 0 && r < 7 && T.vtx < 0) z[7 * (size_t)(T.vtx & 0x7fffffff) + r] = out;
+  }
+  if (T.slot >= 0 && c == 0 && r < 7) ybuf[7 * T.slot + r] = out;
+}
+
+template <int BWD, int MB, int D>
+__global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* __restrict__ sub_lvl,
+                                                               const int32_t* __restrict__ wtask,
+                                                               const int4* __restrict__ task,
+                                                               const int2* __restrict__ aux,
+                                                               const int32_t* __restrict__ lslot,
+                                                               const double* __restrict__ fac,
+                                                               const double* __restrict__ v, double* yl,
+                                                               double* __restrict__ z, int nslots) {
+  extern __shared__ double lds[];
+  double* ybuf = lds;                          // [nslots][7]
+  const int s = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* scr = lds + 7 * (size_t)nslots + 8 * wave;   // [8] per wavefront
+  const int r = lane >> 3, c = lane & 7;
+  const int e = 7 * (r < 7 ? r : 6) + (c < 7 ? c : 6);   // block entry of the lane
+  const int voff = (r < 7 && c < 7) ? 8 * e : kOutside;
+  const char* ybuf_c = (const char*)ybuf + 8 * (c < 7 ? c : 6);
+  const int nL = sub_lvl[s + 1] - sub_lvl[s];
+  // slots are read before their first write only through blocks with A = 0: keep them finite
+  for (int t = threadIdx.x; t < 7 * nslots; t += 64 * kSweepWaves) ybuf[t] = 0.0;
+  __syncthreads();
+  const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
+  int cur = 0;  // level barriers passed
+  if (te > tb) {
+    // c0 holds tasks [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
+    // D - 1 tasks, so task t and the task t + D - 1 loaded with it always share c0 and c1
+    // is touched only when it becomes c0, long after its load.
+    constexpr int kStride = 64 - (D - 1);
+    int cb = tb;
+    TaskChunk c0 = load_chunk(task, aux, cb, te, lane);
+    TaskChunk c1 = load_chunk(task, aux, cb + kStride, te, lane);
+    TaskData<MB> buf[D];
+#pragma unroll
+    for (int k = 0; k + 1 < D; ++k) {
+      const int u = tb + k < te ? tb + k : te - 1;
+      task_load<BWD, MB>(buf[k], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
+    }
+    for (int t0 = tb; t0 < te; t0 += D) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int t = t0 + k;
+        if (t < te && t + D - 1 - cb == 64) {  // the chunk at cb + kStride starts at task t
+          c0 = c1;
+          cb += kStride;
+          c1 = load_chunk(task, aux, cb + kStride, te, lane);
+        }
+        const int u = t + D - 1 < te ? t + D - 1 : te - 1;
+        task_load<BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
+        if (t < te) {
+          const TaskMeta T = chunk_get(c0, t - cb);
+          while (cur < T.level) {
+            lds_barrier();
+            ++cur;
+          }
+          task_run<BWD, MB>(T, buf[k], lslot, fac, ybuf_c, ybuf, scr, yl, z, lane, e, r, c);
+        }
+      }
+    }
+  }
+  while (cur < nL) {  // every wavefront passes the same number of barriers
+    lds_barrier();
+    ++cur;
+  }
+}
+
+template <int MB, int D>
+static hipError_t launch_sweeps(fsi_solver* s, const double* v, double* z) {
+  constexpr int NT = 64 * kSweepWaves;
+  const size_t lds = (size_t)s->h.nslots * 7 * sizeof(double) + kSweepWaves * 8 * sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ilu_sweep<0, MB, D>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_ilu_sweep<1, MB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e != hipSuccess) return e;
+  }
   FSI_PROF_LAUNCH(s, "ilu_fwd",
-                  hipLaunchKernelGGL(k_ilu_fwd, dim3(s->h.ns), dim3(512), 0, s->stream, s->fwd_sub_lvl, s->fwd_lvl_ptr,
-                                     s->fwd_rows, s->lrowptr, s->ldiag, s->lcol, s->lglob, s->fac, v, s->ylocal));
+                  hipLaunchKernelGGL((k_ilu_sweep<0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
+                                     s->fwd_sub_lvl, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, s->fac,
+                                     v, s->ylocal, z, s->h.nslots));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
-                  hipLaunchKernelGGL(k_ilu_bwd, dim3(s->h.ns), dim3(512), 0, s->stream, s->bwd_sub_lvl, s->bwd_lvl_ptr,
-                                     s->bwd_rows, s->lrowptr, s->ldiag, s->lcol, s->lglob, s->lowned, s->fac,
-                                     s->ylocal, z));
+                  hipLaunchKernelGGL((k_ilu_sweep<1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
+                                     s->bwd_sub_lvl, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, s->fac,
+                                     v, s->ylocal, z, s->h.nslots));
   return hipGetLastError();
+}
+
+// Prefetched blocks per row from the longest L or U part of any row (longer rows read the
+// rest on demand); short rows keep three tasks in flight, long rows two.
+hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
+  const int longest = s->max_lblk > s->max_ublk ? s->max_lblk : s->max_ublk;
+  if (longest <= 16) return launch_sweeps<16, 3>(s, v, z);
+  return launch_sweeps<32, 3>(s, v, z);
 }
 
 }  // namespace fsi

