@@ -2,9 +2,9 @@
 
 Workload: the seeded synthetic bifurcating compliant tree of depth 3 (8 outlets, radius
 ratio 0.79, branch angles 25-45 deg, one-lattice-cell wall), about 203k vertices and 1.37M
-active unknowns, pulsatile inflow 30 + 15 sin(2 pi t / 0.8) cm/s, traction-free outlets,
+active unknowns, pulsatile inflow 30 + 15 sin(2 pi t / 0.8) cm/s, traction-free planar outlets,
 dt = 1e-3 s, 64 restricted additive Schwarz subdomains with overlap 1 and block ILU(l)
-subdomain solves (l = 2 by default: ILU(0) and ILU(1) stall GMRES(30) on this wall).
+subdomain solves (l = 3 by default: lower fill levels stall GMRES(30) on this wall).
 
 A step is one whole Newton-Krylov-Schwarz solve (residuals, exact Jacobians, Schwarz
 setups, GMRES iterations, line searches) through the library's C ABI.  Before the warmup
@@ -36,17 +36,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pcapply_bytes(s) -> tuple[int, dict]:
-    """Algorithmic HBM bytes of one Schwarz application (forward + backward sweep):
-    factor blocks once (392 B + a 4 B column index each), per-row index data, the gathered
-    input, the local vector written and re-read, and the owned output."""
+def sweep_bytes(s) -> dict:
+    """Algorithmic HBM bytes of one launch of each triangular sweep of the Schwarz solve.
+
+    forward  (y = L^-1 R v): strict-L blocks (392 B each) and their column slot (4 B), a
+             24 B task record per local row, the gathered input (7 doubles per local row)
+             and y written (7 doubles per local row);
+    backward (x = U^-1 y): strict-U blocks and the inverted diagonal of every row (392 B
+             each), the U column slots, the task records, y read, and the owned rows of z
+             written (7 doubles per vertex).
+    """
     pc = s.pc_get(factors=False)
-    NB = len(pc["lcolind"])
-    R = len(pc["sub_verts"])
     ns = len(pc["sub_nowned"])
-    V = s.V
-    b = NB * (49 * 8 + 4) + 4 * (R + ns) + 7 * R * 8 * 3 + 7 * V * 8
-    return b, dict(local_blocks=NB, local_rows=R)
+    rp = pc["lrowptr"].astype(np.int64)
+    col = pc["lcolind"].astype(np.int64)
+    nL = 0
+    for k in range(ns):
+        r0 = int(pc["sub_ptr"][k]) + k          # row pointers of subdomain k start here
+        n_k = int(pc["sub_ptr"][k + 1] - pc["sub_ptr"][k])
+        ptr = rp[r0:r0 + n_k + 1]
+        b0 = int(pc["blk_ptr"][k])
+        rows = np.repeat(np.arange(n_k), np.diff(ptr))
+        nL += int(np.count_nonzero(col[b0 + ptr[0]:b0 + ptr[-1]] < rows))
+    NB = len(col)
+    R = len(pc["sub_verts"])
+    nU = NB - R - nL
+    fwd = nL * (392 + 4) + 24 * R + 2 * 56 * R
+    bwd = (nU + R) * 392 + 4 * nU + 24 * R + 56 * R + 56 * s.V
+    return dict(ilu_fwd=fwd, ilu_bwd=bwd, local_blocks=NB, local_rows=R, l_blocks=nL, u_blocks=nU)
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the profile on record was
+    taken with the current sweep source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    src = open(os.path.join(ROOT, "paper_1810_04289_amd", "csrc", "ilu.hip"), "rb").read()
+    if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
 
 
 def spmv_bytes(s) -> int:
@@ -111,9 +144,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--depth", type=int, default=3)
     ap.add_argument("--nsub", type=int, default=64)
-    ap.add_argument("--ilu", type=int, default=2)
+    ap.add_argument("--ilu", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, run a plain elementwise copy of this many MiB three times "
+                         "(reference dispatch for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -157,6 +193,14 @@ def main():
         st = step(k)
         log(f"[bench] warmup step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
 
+    if args.calib_copy_mib > 0:
+        a = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
     s.prof_enable(True)
     torch.cuda.synchronize()
     stats = []
@@ -176,9 +220,12 @@ def main():
         kernels[name] = {"total_ms": round(ms, 3), "count": cnt, "avg_us": round(1e3 * ms / cnt, 2) if cnt else None}
     s.prof_enable(False)
 
-    pb, pinfo = pcapply_bytes(s)
-    t_pair = (kernels["ilu_fwd"]["avg_us"] or 0) + (kernels["ilu_bwd"]["avg_us"] or 0)
-    achieved = pb / (t_pair * 1e-6) / 1e9 if t_pair else None
+    sw = sweep_bytes(s)
+    dom = max(("ilu_fwd", "ilu_bwd"), key=lambda k: kernels[k]["total_ms"])
+    t_dom = kernels[dom]["avg_us"]
+    achieved = sw[dom] / (t_dom * 1e-6) / 1e9 if t_dom else None
+    other = "ilu_bwd" if dom == "ilu_fwd" else "ilu_fwd"
+    t_other = kernels[other]["avg_us"]
     sb = spmv_bytes(s)
     spmv_gbs = sb / (kernels["spmv"]["avg_us"] * 1e-6) / 1e9 if kernels["spmv"]["avg_us"] else None
 
@@ -199,12 +246,16 @@ def main():
                                f"{mesh.ntets} tets, {s.n} unknowns, dt {dt}, {args.nsub} RAS subdomains overlap 1, "
                                f"ILU({args.ilu}), GMRES(30) rtol 1e-3, Newton rtol 1e-6",
                    "nverts": mesh.nverts, "ntets": mesh.ntets, "n": s.n, "nnzb": s.nnzb, "nsub": args.nsub,
-                   "ilu_level": args.ilu, "dt": dt, **pinfo},
+                   "ilu_level": args.ilu, "dt": dt, "local_blocks": sw["local_blocks"],
+                   "local_rows": sw["local_rows"]},
         "NI": NI, "LI": round(LI, 2), "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
-        "roofline": {"bound": "hbm", "kernel": "ilu_fwd+ilu_bwd (one Schwarz application)",
+        "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK, 4) if achieved else None, "traffic": None,
-                     "bytes_per_launch": pb, "avg_us": round(t_pair, 2)},
+                     "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
+                     "traffic": stored_traffic(dom), "bytes_per_launch": sw[dom], "avg_us": t_dom,
+                     "other_sweep": {"kernel": other, "bytes_per_launch": sw[other], "avg_us": t_other,
+                                     "achieved": round(sw[other] / (t_other * 1e-6) / 1e9, 1) if t_other else None,
+                                     "traffic": stored_traffic(other)}},
         "spmv": {"achieved_GBs": round(spmv_gbs, 1) if spmv_gbs else None, "bytes": sb,
                  "frac": round(spmv_gbs / HBM_PEAK, 4) if spmv_gbs else None},
         "kernels": kernels,

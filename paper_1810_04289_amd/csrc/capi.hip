@@ -404,6 +404,8 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->bwd_rows = upload(s, h.bwd_rows);
   {
     // per-wavefront task lists of both sweeps (level order inside each wavefront)
+    s->sweep_mb = sweep_task_blocks(std::max(s->max_lblk, s->max_ublk));
+    const int mb = s->sweep_mb;
     auto tasks = [&](bool bwd, const std::vector<int32_t>& sub_lvl, const std::vector<int32_t>& lvl_ptr,
                      const std::vector<int32_t>& rows, const std::vector<int32_t>& qslot, int32_t** wtask_d,
                      int4** task_d, int2** aux_d) {
@@ -418,9 +420,16 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
             for (int q = lvl_ptr[L] + w; q < lvl_ptr[L + 1]; q += kSweepWaves) {
               const int i = rows[q];
               const int g = h.lglob[i] | (h.lowned[i] ? (int)0x80000000u : 0);
-              task.push_back(bwd ? make_int4(i, g, h.ldiag[i], h.lrowptr[i + 1])
-                                 : make_int4(i, g, h.lrowptr[i], h.ldiag[i]));
-              aux.push_back(make_int2(qslot[q], L - sub_lvl[sd]));
+              const int b0 = bwd ? h.ldiag[i] + 1 : h.lrowptr[i], b1 = bwd ? h.lrowptr[i + 1] : h.ldiag[i];
+              const int nc = std::max(1, (b1 - b0 + mb - 1) / mb);
+              for (int c = 0; c < nc; ++c) {
+                // backward: chunks from the row's end, so the one next to D_i comes last
+                const int k = bwd ? nc - 1 - c : c;
+                const int f = b0 + k * mb, l = std::min(b1, f + mb);
+                const int flags = (c > 0 ? (1 << 28) : 0) | (c + 1 < nc ? (1 << 29) : 0);
+                task.push_back(make_int4(i, g, f, l));
+                aux.push_back(make_int2(qslot[q], (L - sub_lvl[sd]) | flags));
+              }
             }
           wtask[sd * kSweepWaves + w + 1] = (int32_t)task.size();
         }

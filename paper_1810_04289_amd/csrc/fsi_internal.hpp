@@ -102,9 +102,11 @@ struct fsi_solver {
   int32_t *bwd_sub_lvl = nullptr, *bwd_lvl_ptr = nullptr, *bwd_rows = nullptr;
   // sweep task lists: the rows of a subdomain's level go to its kSweepWaves wavefronts
   // round-robin; wavefront w of subdomain s takes tasks [wtask[s*kSweepWaves + w],
-  // wtask[s*kSweepWaves + w + 1]) in level order.  task = {row, global vertex (bit 31 =
-  // owned), first, last} (forward: L blocks [first, last); backward: D at first, U blocks
-  // (first, last)); task_aux = {own LDS slot or -1, level within the subdomain}.
+  // wtask[s*kSweepWaves + w + 1]) in level order.  A row is one task per sweep_mb of its
+  // strict blocks.  task = {row, global vertex (bit 31 = owned), first, last}: the task's
+  // blocks [first, last) (forward: L; backward: U, the chunk next to D_i last);
+  // task_aux = {own LDS slot or -1, level | continues-row bit 28 | row-continues bit 29}.
+  int sweep_mb = 0;
   int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr;
   int4 *fwd_task = nullptr, *bwd_task = nullptr;
   int2 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
@@ -134,6 +136,7 @@ hipError_t launch_impose(fsi_solver* s, double* y);
 hipError_t launch_spmv(fsi_solver* s, const double* x, double* y);
 hipError_t launch_pc_setup(fsi_solver* s);
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
+int sweep_task_blocks(int longest_part);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);
 hipError_t launch_vupdate(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n);

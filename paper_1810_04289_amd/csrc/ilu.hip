@@ -268,8 +268,10 @@ hipError_t launch_pc_setup(fsi_solver* s) {
 // a time (one task per lane, broadcast by readlane) and the block values, the column
 // rows' LDS slots and the row's input of task t + D - 1 are requested while task t is
 // computed, into D rotating register sets.  Every task issues the same number of loads
-// (short rows repeat their last block), so the compiler's in-order memory counter waits
-// only for the set about to be used.
+// (blocks beyond the task's range read 0), so the compiler's in-order memory counter waits
+// only for the set about to be used.  A row longer than MB blocks is split into consecutive
+// tasks of at most MB blocks that carry their partial sums in registers; only the last one
+// finishes the row (the backward sweep takes the chunk next to D_i last).
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
@@ -293,7 +295,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 struct TaskMeta {  // one task, uniform across the wavefront
-  int row, vtx, first, last, slot, level;
+  int row, vtx, first, last, slot, lvf;  // lvf: level | kTaskCont | kTaskMore
 };
 
 struct TaskChunk {  // lane j: task base + j
@@ -306,6 +308,10 @@ __device__ __forceinline__ TaskChunk load_chunk(const int4* __restrict__ task, c
   const int q = t + lane < te ? t + lane : te - 1;
   return TaskChunk{task[q], aux[q]};
 }
+
+constexpr int kTaskLevel = (1 << 28) - 1;
+constexpr int kTaskCont = 1 << 28;  // continues the previous task's row
+constexpr int kTaskMore = 1 << 29;  // the row continues in the next task
 
 __device__ __forceinline__ TaskMeta chunk_get(const TaskChunk& c, int l) {
   return TaskMeta{__builtin_amdgcn_readlane(c.m.x, l), __builtin_amdgcn_readlane(c.m.y, l),
@@ -331,8 +337,8 @@ __device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int vo
 
 template <int MB>
 struct TaskData {
-  double A[MB];   // entry (r, c) of the row's first MB blocks; 0 beyond the row and on padding lanes
-  int ls;         // lane b < 64: LDS byte offset of the column row of block b (0 beyond the row)
+  double A[MB];   // entry (r, c) of the task's blocks; 0 beyond its range and on padding lanes
+  int ls;         // lane b < MB: LDS byte offset of the column row of block b (0 beyond the range)
   double base;    // forward: v of the vertex (component r); backward: y_i (component r)
   double D;       // backward: entry (r, c) of D_i (0 on padding lanes)
 };
@@ -342,7 +348,7 @@ template <int BWD, int MB>
 __device__ __forceinline__ void task_load(TaskData<MB>& P, const TaskMeta& T, const int32_t* __restrict__ lslot,
                                           const double* __restrict__ fac, const double* __restrict__ v,
                                           const double* yl, int lane, int voff, int r) {
-  const int first = BWD ? T.first + 1 : T.first;
+  const int first = T.first;
   const int nb = T.last - first;
   // one resource per group of eight blocks keeps every block offset in the immediate field
 #pragma unroll
@@ -356,24 +362,26 @@ __device__ __forceinline__ void task_load(TaskData<MB>& P, const TaskMeta& T, co
   const int rv = r < 7 ? r : 6;
   if (BWD) {
     P.base = yl[7 * (size_t)T.row + rv];
-    P.D = span_load_f64(span_rsrc(fac + 49 * (size_t)T.first, 392), voff);
+    // D_i precedes the row's first U block; chunks other than the last read a U block
+    // here, which they do not use
+    P.D = span_load_f64(span_rsrc(fac + 49 * (size_t)(T.first - 1), 392), voff);
   } else {
     P.base = v[7 * (size_t)(T.vtx & 0x7fffffff) + rv];
   }
 }
 
-// ybuf_c: this lane's component column of the LDS slots (byte address of ybuf + 8c)
+// ybuf_c: this lane's component column of the LDS slots (byte address of ybuf + 8c);
+// acc: the row's partial sums, carried from task to task while a row continues
 template <int BWD, int MB>
-__device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& P, const int32_t* __restrict__ lslot,
-                                         const double* __restrict__ fac, const char* ybuf_c, double* ybuf,
-                                         double* scr, double* yl, double* __restrict__ z, int lane, int e, int r,
+__device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& P, const char* ybuf_c, double* ybuf,
+                                         double* scr, double* yl, double* __restrict__ z, double (&acc)[4], int r,
                                          int c) {
-  const int first = BWD ? T.first + 1 : T.first;
-  const int nb = T.last - first;
+  const int nb = T.last - T.first;
   const int cc = c < 7 ? c : 6;
-  double acc = 0.0;
+  if (!(T.lvf & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
   // groups of eight blocks: the LDS reads of a group are issued together; blocks beyond
-  // the row contribute A = 0 times a finite slot value
+  // the range contribute A = 0 times a finite slot value.  Block b goes to acc[b % 4]:
+  // four independent FMA chains.
 #pragma unroll
   for (int g = 0; g < MB; g += 8) {
     if (g < nb) {
@@ -382,22 +390,18 @@ __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& 
       for (int u = 0; u < 8 && g + u < MB; ++u)
         yv[u] = *(const double*)(ybuf_c + __builtin_amdgcn_readlane(P.ls, g + u));
 #pragma unroll
-      for (int u = 0; u < 8 && g + u < MB; ++u) acc = fma(P.A[g + u], yv[u], acc);
+      for (int u = 0; u < 8 && g + u < MB; ++u) acc[u & 3] = fma(P.A[g + u], yv[u], acc[u & 3]);
     }
   }
-  for (int b = MB; b < nb; ++b) {   // blocks beyond the prefetched ones
-    const int off = b < 64 ? __builtin_amdgcn_readlane(P.ls, b) : lslot[first + b];
-    const double a = fac[49 * (size_t)(first + b) + e];
-    const double yv = *(const double*)(ybuf_c + off);
-    acc += (c < 7 && r < 7) ? a * yv : 0.0;
-  }
-  acc = sum8(acc);                  // sum_c of row r of all blocks times the column values
+  if (T.lvf & kTaskMore) return;
+  // sum_c of row r of all blocks times the column values
+  const double sum = sum8((acc[0] + acc[1]) + (acc[2] + acc[3]));
   double out;
   if (!BWD) {
-    out = P.base - acc;                                   // y_i = b_i - sum_k L_ik y_k
+    out = P.base - sum;                                   // y_i = b_i - sum_k L_ik y_k
     if (c == 0 && r < 7) yl[7 * (size_t)T.row + r] = out;
   } else {
-    const double t = P.base - acc;                        // y_i - sum_j U_ij x_j
+    const double t = P.base - sum;                        // y_i - sum_j U_ij x_j
     if (c == 0 && r < 7) scr[r] = t;
     wave_lds_sync();
     const double tc = scr[cc];
@@ -433,6 +437,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   __syncthreads();
   const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
   int cur = 0;  // level barriers passed
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (te > tb) {
     // c0 holds tasks [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
     // D - 1 tasks, so task t and the task t + D - 1 loaded with it always share c0 and c1
@@ -460,11 +465,12 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
         task_load<BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
         if (t < te) {
           const TaskMeta T = chunk_get(c0, t - cb);
-          while (cur < T.level) {
+          const int level = T.lvf & kTaskLevel;
+          while (cur < level) {
             lds_barrier();
             ++cur;
           }
-          task_run<BWD, MB>(T, buf[k], lslot, fac, ybuf_c, ybuf, scr, yl, z, lane, e, r, c);
+          task_run<BWD, MB>(T, buf[k], ybuf_c, ybuf, scr, yl, z, acc, r, c);
         }
       }
     }
@@ -499,12 +505,18 @@ static hipError_t launch_sweeps(fsi_solver* s, const double* v, double* z) {
   return hipGetLastError();
 }
 
-// Prefetched blocks per row from the longest L or U part of any row (longer rows read the
-// rest on demand); short rows keep three tasks in flight, long rows two.
+// Blocks per sweep task (rows are split into tasks of at most this many blocks) and the
+// matching kernels: the tasks in flight per wavefront shrink as tasks grow, keeping the
+// prefetched blocks within the register file.
+int sweep_task_blocks(int longest_part) { return longest_part <= 16 ? 16 : 24; }
+
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
-  const int longest = s->max_lblk > s->max_ublk ? s->max_lblk : s->max_ublk;
-  if (longest <= 16) return launch_sweeps<16, 3>(s, v, z);
-  return launch_sweeps<32, 3>(s, v, z);
+  switch (s->sweep_mb) {
+    case 16: return launch_sweeps<16, 4>(s, v, z);
+    case 24: return launch_sweeps<24, 3>(s, v, z);
+    case 32: return launch_sweeps<32, 2>(s, v, z);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace fsi

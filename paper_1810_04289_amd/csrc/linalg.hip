@@ -48,14 +48,16 @@ __global__ void __launch_bounds__(256) k_dot_partial(const double* __restrict__ 
   if (threadIdx.x == 0) partial[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
 
-// out[k] = sum_b partial[b*stride + k] for k < nk, in block order
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nb, int stride, int nk,
-                                  double* __restrict__ out) {
-  int k = threadIdx.x;
-  if (k >= nk) return;
+// out[k] = sum_b partial[b*stride + k], one wavefront per k (grid nk): lane j sums the
+// partials j, j+64, ... and a fixed wavefront tree adds the lanes, so the order is fixed
+__global__ void __launch_bounds__(64) k_reduce_partials(const double* __restrict__ partial, int nb, int stride,
+                                                        double* __restrict__ out) {
+  const int k = blockIdx.x;
   double acc = 0.0;
-  for (int b = 0; b < nb; ++b) acc += partial[(size_t)b * stride + k];
-  out[k] = acc;
+#pragma unroll 16
+  for (int b = threadIdx.x; b < nb; b += 64) acc += partial[(size_t)b * stride + k];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) out[k] = acc;
 }
 
 // Multi-dot of one Gram-Schmidt pass: partial[b*32 + i] for i < nv (nv <= 32).
@@ -128,7 +130,7 @@ hipError_t launch_spmv(fsi_solver* s, const double* x, double* y) {
 
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out) {
   hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s->stream, a, b, n, s->partial);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s->stream, s->partial, kRedBlocks, 1, 1, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s->stream, s->partial, kRedBlocks, 1, out);
   return hipGetLastError();
 }
 
@@ -138,7 +140,7 @@ hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w,
     FSI_PROF_LAUNCH(s, "mdot",
                     hipLaunchKernelGGL(k_mdot_partial, dim3(kRedBlocks), dim3(256), 0, s->stream,
                                        Vb + (size_t)i0 * n, c, n, w, s->partial));
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s->stream, s->partial, kRedBlocks, 32, c, h + i0);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(c), dim3(64), 0, s->stream, s->partial, kRedBlocks, 32, h + i0);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,147 @@
+"""Summarise rocprofv3 output of the benchmark into short text records.
+
+Reads a kernel-trace run (``--kernel-trace --stats``, CSV) and two counter runs
+(``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE``, CSV) of ``bench.py --calib-copy-mib N``
+and writes:
+
+* a Markdown summary (per-kernel call counts and durations, HBM bytes per launch of the
+  triangular sweeps, the commands that produced them);
+* a JSON record of the sweeps' HBM bytes per launch, tagged with the SHA-256 of the sweep
+  source it was measured with (``bench.py`` reports it only while the source is unchanged).
+
+FETCH_SIZE and WRITE_SIZE are scaled by what they read for the calibration dispatch, a
+plain elementwise copy of known size (N MiB read, N MiB written).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SWEEPS = {"ilu_fwd": "k_ilu_sweep<0", "ilu_bwd": "k_ilu_sweep<1"}
+
+
+def _one(d: str, pattern: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def counter_values(d: str, counter: str) -> list[tuple[str, float]]:
+    """(kernel name, counter value) per dispatch, in dispatch order."""
+    rows = []
+    with open(_one(d, "*counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((int(r.get("Dispatch_Id", 0)), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def calib_factor(vals: list[tuple[str, float]], nbytes: int) -> float:
+    """Counter bytes per algorithmic byte on the calibration copy: the three largest
+    dispatches of kernels outside the library."""
+    other = sorted((v for k, v in vals if "fsi::" not in k), reverse=True)[:3]
+    if len(other) < 3:
+        raise RuntimeError("calibration copy dispatches not found")
+    return statistics.median(other) * 1024.0 / nbytes
+
+
+def sweep_bytes(vals: list[tuple[str, float]], factor: float) -> dict:
+    out = {}
+    for name, tag in SWEEPS.items():
+        v = [x for k, x in vals if tag in k]
+        if v:
+            out[name] = dict(dispatches=len(v), mean_kib=statistics.mean(v),
+                             bytes_per_launch=statistics.mean(v) * 1024.0 / factor)
+    return out
+
+
+def kernel_stats(d: str, top: int = 14) -> list[dict]:
+    rows = []
+    with open(_one(d, "*kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append(dict(name=r["Name"], calls=int(r["Calls"]), total_ms=float(r["TotalDurationNs"]) / 1e6,
+                             avg_us=float(r["AverageNs"]) / 1e3, pct=float(r["Percentage"])))
+    rows.sort(key=lambda x: -x["total_ms"])
+    return rows[:top]
+
+
+def short(name: str) -> str:
+    n = name.split("(")[0]
+    return n if len(n) <= 70 else n[:67] + "..."
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace-dir", required=True)
+    ap.add_argument("--fetch-dir", required=True)
+    ap.add_argument("--write-dir", required=True)
+    ap.add_argument("--copy-mib", type=int, required=True)
+    ap.add_argument("--trace-cmd", required=True)
+    ap.add_argument("--fetch-cmd", required=True)
+    ap.add_argument("--write-cmd", required=True)
+    ap.add_argument("--algo-bytes", default="", help="JSON of the bench line with the algorithmic bytes")
+    ap.add_argument("--out-md", required=True)
+    ap.add_argument("--out-json", required=True)
+    a = ap.parse_args()
+
+    nbytes = a.copy_mib << 20
+    fv = counter_values(a.fetch_dir, "FETCH_SIZE")
+    wv = counter_values(a.write_dir, "WRITE_SIZE")
+    ff, wf = calib_factor(fv, nbytes), calib_factor(wv, nbytes)
+    fb, wb = sweep_bytes(fv, ff), sweep_bytes(wv, wf)
+    algo = {}
+    if a.algo_bytes:
+        line = json.load(open(a.algo_bytes))
+        rl = line["roofline"]
+        algo[rl["kernel"]] = rl["bytes_per_launch"]
+        algo[rl["other_sweep"]["kernel"]] = rl["other_sweep"]["bytes_per_launch"]
+    kern = {}
+    for k in SWEEPS:
+        if k in fb and k in wb:
+            kern[k] = dict(fetch_bytes_per_launch=round(fb[k]["bytes_per_launch"]),
+                           write_bytes_per_launch=round(wb[k]["bytes_per_launch"]),
+                           hbm_bytes_per_launch=round(fb[k]["bytes_per_launch"] + wb[k]["bytes_per_launch"]),
+                           dispatches=fb[k]["dispatches"])
+            if k in algo:
+                kern[k]["algorithmic_bytes_per_launch"] = algo[k]
+                kern[k]["traffic_over_algorithmic"] = round(kern[k]["hbm_bytes_per_launch"] / algo[k], 3)
+    src = open(os.path.join(HERE, "csrc", "ilu.hip"), "rb").read()
+    rec = dict(ilu_hip_sha256=hashlib.sha256(src).hexdigest(), copy_mib=a.copy_mib,
+               fetch_scale=round(ff, 4), write_scale=round(wf, 4), kernels=kern,
+               commands=dict(fetch=a.fetch_cmd, write=a.write_cmd))
+    with open(a.out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+
+    ks = kernel_stats(a.trace_dir)
+    L = ["# Triangular sweeps and the NKS step on the depth-3 tree: rocprofv3 summary", "",
+         "Kernel trace (`--kernel-trace --stats`), command:", "", f"    {a.trace_cmd}", "",
+         "| kernel | calls | total ms | avg us | % |", "|---|---:|---:|---:|---:|"]
+    L += [f"| `{short(r['name'])}` | {r['calls']} | {r['total_ms']:.1f} | {r['avg_us']:.1f} | {r['pct']:.1f} |"
+          for r in ks]
+    L += ["", "HBM bytes per launch from `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), each scaled by "
+          f"what it reads for a plain elementwise copy of {a.copy_mib} MiB (fetch scale {ff:.4f}, write "
+          f"scale {wf:.4f} counter bytes per copied byte). Commands:", "", f"    {a.fetch_cmd}",
+          f"    {a.write_cmd}", "",
+          "| kernel | dispatches | fetch MB | write MB | HBM MB | algorithmic MB | ratio |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, v in kern.items():
+        al = v.get("algorithmic_bytes_per_launch")
+        L.append(f"| {k} | {v['dispatches']} | {v['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                 f"{v['write_bytes_per_launch'] / 1e6:.1f} | {v['hbm_bytes_per_launch'] / 1e6:.1f} | "
+                 f"{al / 1e6 if al else float('nan'):.1f} | {v.get('traffic_over_algorithmic', float('nan'))} |")
+    L += ["", f"Sweep source SHA-256: `{rec['ilu_hip_sha256']}`", ""]
+    with open(a.out_md, "w") as f:
+        f.write("\n".join(L))
+
+
+if __name__ == "__main__":
+    main()

@@ -369,16 +369,27 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
     cen = (lat_xyz(T[:, 0]) + lat_xyz(T[:, 1]) + lat_xyz(T[:, 2]) + lat_xyz(T[:, 3])) / 4.0
     sdf = np.full(len(T), np.inf)
     void = np.zeros(len(T), dtype=bool)
+    planes = []  # (axis, lattice index) of each outlet plane
     for b in br:
         t, d = _seg_param(cen, b.A, b.B)
         L = np.linalg.norm(d)
         if b.terminal:
-            tc = np.clip(t, 0.0, 1.0)
-            axial_beyond = (t - 1.0) * L
-            radial = np.linalg.norm(cen - (b.A[None] + np.clip(t, 0, None)[:, None] * d[None]), axis=1)
-            void |= (axial_beyond > 0) & (axial_beyond < margin) & (radial < b.r + margin)
-            ds = np.linalg.norm(cen - (b.A[None] + tc[:, None] * d[None]), axis=1) - b.r
-            ds = np.where(t > 1.0, np.inf, ds)
+            # The outlet is the lattice plane nearest the branch end, normal to the lattice
+            # axis closest to the branch direction: whole cube faces, so the cap is planar.
+            # The branch cylinder is continued past its end until it crosses that plane.
+            dn = d / L
+            ax = int(np.argmax(np.abs(dn)))
+            sg = 1.0 if dn[ax] > 0 else -1.0
+            kp = int(round((b.B[ax] - lo[ax]) / h))
+            cpl = lo[ax] + kp * h
+            planes.append((ax, kp))
+            ext = (b.r + margin) * math.sqrt(max(1.0 - dn[ax] ** 2, 0.0)) / abs(dn[ax]) + 2 * h
+            tmax = 1.0 + ext / L
+            tc = np.clip(t, 0.0, tmax)
+            radial = np.linalg.norm(cen - (b.A[None] + tc[:, None] * d[None]), axis=1)
+            beyond = sg * (cen[:, ax] - cpl) > 0
+            void |= beyond & (t > 0.5) & (radial < b.r + margin)
+            ds = np.where(beyond & (t > 0.5), np.inf, radial - b.r)
         else:
             tc = np.clip(t, 0.0, 1.0)
             ds = np.linalg.norm(cen - (b.A[None] + tc[:, None] * d[None]), axis=1) - b.r
@@ -401,11 +412,17 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
     Xl = lat_xyz(np.arange(int(n1.prod())))
     X, tets, used = _compact(Xl, Tm)
     ktop = (used // (n1[0] * n1[1])) == nz
+    lidx = np.stack([used % n1[0], (used // n1[0]) % n1[1], used // (n1[0] * n1[1])], 1)
+    # vertices of outlet caps (faces shared with void tets) stay in their plane
+    vkeys = np.array(sorted(vset), dtype=np.int64).reshape(-1, 3) if vset else np.zeros((0, 3), np.int64)
+    on_cap = np.isin(used, np.unique(vkeys))
 
-    # seeded jitter (5% of h); top-plane vertices move in-plane only
+    # seeded jitter (5% of h); inlet-plane and outlet-plane vertices move in-plane only
     rng = np.random.default_rng(seed + 1)
     dX = jitter * h * rng.uniform(-1.0, 1.0, size=X.shape)
     dX[ktop, 2] = 0.0
+    for ax, kp in planes:
+        dX[on_cap & (lidx[:, ax] == kp), ax] = 0.0
     X = X + dX
     tets = _orient(X, tets).astype(np.int32)
 
