@@ -445,12 +445,26 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     for (size_t p = 0; p < lbyte.size(); ++p) lbyte[p] = h.lslot[p] >= 0 ? 56 * h.lslot[p] : 0;
     s->lslot = upload(s, lbyte);
   }
-  s->kent_ptr = upload(s, h.kent_ptr);
-  s->kent_ik = upload(s, h.kent_ik);
-  s->kent_dk = upload(s, h.kent_dk);
-  s->kent_tptr = upload(s, h.kent_tptr);
-  s->tri_kj = upload(s, h.tri_kj);
-  s->tri_ij = upload(s, h.tri_ij);
+  {
+    // factorization groups: per pivot, U_k in runs of up to 2*kFacHalf blocks
+    std::vector<int32_t> gptr(1, 0);
+    std::vector<int4> grp;
+    for (size_t i = 0; i + 1 < h.kent_ptr.size(); ++i) {
+      for (int k = h.kent_ptr[i]; k < h.kent_ptr[i + 1]; ++k) {
+        const int pik = h.piv[4 * k], dk = h.piv[4 * k + 1], nu = h.piv[4 * k + 2], mo = h.piv[4 * k + 3];
+        const int run = 2 * kFacHalf;
+        const int ngk = std::max(1, (nu + run - 1) / run);
+        for (int g = 0; g < ngk; ++g) {
+          const int nb = std::min(run, nu - run * g);
+          grp.push_back(make_int4(dk + 1 + run * g, dk, mo + run * g, (pik << 6) | (std::max(nb, 0) << 1) | (g == 0)));
+        }
+      }
+      gptr.push_back((int32_t)grp.size());
+    }
+    s->fgrp_ptr = upload(s, gptr);
+    s->fgrp = upload(s, grp);
+  }
+  s->umap = upload(s, h.umap);
   s->sub_row_off = upload(s, h.sub_row_off);
   s->fac = dalloc<double>(s, (size_t)s->NB * 49);
   s->udiag = dalloc<double>(s, (size_t)s->R * 49);

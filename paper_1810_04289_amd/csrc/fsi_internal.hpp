@@ -18,6 +18,7 @@ enum : uint8_t { RK_ELEM = 0, RK_DIR = 1, RK_KIN = 2, RK_DUMMY = 3 };
 constexpr int kMaxRestart = 200;
 constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic sums
 constexpr int kSweepWaves = 8;    // wavefronts per subdomain in the triangular sweeps
+constexpr int kFacHalf = 9;      // factorization group: 2 * kFacHalf U blocks, lane q < 63 takes two
 
 // Host-side setup products (independent of any device state).
 struct HostSetup {
@@ -52,10 +53,12 @@ struct HostSetup {
   // rows[lvl_ptr[sub_lvl[s] + l] .. lvl_ptr[sub_lvl[s] + l + 1])
   std::vector<int32_t> fwd_sub_lvl, fwd_lvl_ptr, fwd_rows;
   std::vector<int32_t> bwd_sub_lvl, bwd_lvl_ptr, bwd_rows;
-  // factorization work lists
-  std::vector<int32_t> kent_ptr;       // [R+1]
-  std::vector<int32_t> kent_ik, kent_dk, kent_tptr;  // [K], [K], [K+1]
-  std::vector<int32_t> tri_kj, tri_ij;               // [T]
+  // factorization work lists: row i's pivots are piv[4*kent_ptr[i] .. 4*kent_ptr[i+1]),
+  // each {position of A_ik in row i, D_k block, length n of U_k, offset o into umap};
+  // umap[o + t] = 1 + position in row i of the block matching U_k's t-th block, or 0
+  std::vector<int32_t> kent_ptr;  // [R+1]
+  std::vector<int32_t> piv;       // [4K]
+  std::vector<int32_t> umap;      // [sum of the pivots' U lengths]
   // LDS slots of the sweeps: a row's result occupies a slot from its level to the level
   // of its last reader (interval colouring per subdomain and direction).
   std::vector<int32_t> fwd_qslot, bwd_qslot;  // per schedule slot: own LDS slot or -1 (no reader)
@@ -111,8 +114,11 @@ struct fsi_solver {
   int4 *fwd_task = nullptr, *bwd_task = nullptr;
   int2 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
   int32_t* lslot = nullptr;  // per block: LDS byte offset (56 * slot) of its column row's slot
-  int32_t *kent_ptr = nullptr, *kent_ik = nullptr, *kent_dk = nullptr, *kent_tptr = nullptr;
-  int32_t *tri_kj = nullptr, *tri_ij = nullptr;
+  // factorization groups: row i's are fgrp[fgrp_ptr[i] .. fgrp_ptr[i+1]), for each pivot k
+  // (ascending) U_k in runs of up to 2*kFacHalf blocks (one run if U_k is empty):
+  // {first U block, D_k block, map offset, (position of A_ik << 6) | (blocks << 1) | first run}
+  int32_t *fgrp_ptr = nullptr, *umap = nullptr;
+  int4* fgrp = nullptr;
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
   // Krylov / Newton work vectors

@@ -37,8 +37,6 @@ __global__ void __launch_bounds__(256) k_ilu_gather(int64_t nb, const int32_t* _
   fac[gid] = src >= 0 ? vals[49 * (size_t)src + e] : 0.0;
 }
 
-constexpr int kTri = 8;  // update pairs in flight per wavefront
-
 // Wavefront-scope ordering of LDS accesses between lanes of one wavefront (LDS operations
 // of a wavefront are processed in order; the fences keep the compiler from reordering).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -47,23 +45,82 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Factorization of one subdomain per workgroup, one row per wavefront.  The row being
-// factored is staged in the wavefront's LDS slice (maxrow blocks), so every access to it
-// during the pivot loop is an LDS access; pivot rows k (final) and D_k are read from
-// memory.  The row's pivot list is read once (one lane per pivot) and broadcast with
-// readlane; while pivot e is applied, pivot e+1's D_k column, its (U_kj, A_ij) index
-// pairs and its first kTri U_kj columns are already in flight.
-template <int NT>
+// Raw buffer loads: a resource spans exactly the bytes a task may read, and the hardware
+// returns 0 for a lane whose offset (vector offset + immediate) falls outside it, without
+// touching memory.  Padding lanes use an offset that is always outside.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+constexpr int kOutside = (int)0x80000000u;
+
+// The arguments are uniform; readfirstlane keeps the descriptor in scalar registers even
+// where the compiler computed a piece of it with vector instructions.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int bytes) {
+  const uint64_t a = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+  void* q = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes), kBufFlags);
+}
+
+__device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int voff) {
+  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
+  return __hiloint2double((int)v.y, (int)v.x);
+}
+
+constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
+
+struct FacDesc {  // one factorization group, uniform across the wavefront (see fsi_internal.hpp)
+  int ublock, dk, moff, flags;
+};
+
+__device__ __forceinline__ FacDesc desc_get(const int4& c, int l) {
+  return FacDesc{__builtin_amdgcn_readlane(c.x, l), __builtin_amdgcn_readlane(c.y, l),
+                 __builtin_amdgcn_readlane(c.z, l), __builtin_amdgcn_readlane(c.w, l)};
+}
+
+struct FacGroup {     // what a group reads from memory
+  double u[2][7];     // lane q < 63: U_kj[m][q % 7] of the group's blocks q / 7 and 9 + q / 7
+  double d;           // lane e < 49: entry e of D_k
+  int pos[2];         // 1 + position of A_ij of those blocks in the row, or 0 (none / beyond U_k)
+};
+
+// A group reads up to 18 consecutive blocks of U_k, their map entries and D_k.  The
+// resources end where the group's data end, so missing blocks, padding lanes and groups
+// past the row's end read 0 without touching memory; every group issues the same 17 loads.
+__device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bool real,
+                                               const double* __restrict__ fac, const int32_t* __restrict__ umap,
+                                               int voff_u, int voff_d, int lane) {
+  const int nblk = real ? (F.flags >> 1) & 31 : 0;
+  const __amdgpu_buffer_rsrc_t ru = span_rsrc(fac + 49 * (size_t)F.ublock, 392 * nblk);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int m = 0; m < 7; ++m) G.u[h][m] = span_load_f64(ru, voff_u + 392 * kFacHalf * h + 56 * m);
+  G.d = span_load_f64(span_rsrc(fac + 49 * (size_t)F.dk, real ? 392 : 0), voff_d);
+  const __amdgpu_buffer_rsrc_t rm = span_rsrc(umap + F.moff, 4 * nblk);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    G.pos[h] = (int)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (lane / 7) + 4 * kFacHalf * h, 0, 0);
+}
+
+// Factorization of one subdomain per workgroup, one row per wavefront, block IKJ order.
+// The row being factored is staged in the wavefront's LDS slice (maxrow blocks).  Its
+// work is a list of groups built on the host: for each pivot k (ascending), U_k in groups
+// of up to 18 blocks (one group if U_k is empty).  The first group of a pivot forms
+// L_ik = A_ik D_k with lane e < 49 holding entry e, writes it back and reads it into every
+// lane; each group then applies A_ij -= L_ik U_kj to its blocks, lane q < 63 holding column
+// q % 7 of blocks q / 7 and 9 + q / 7 (98 FMAs and 14 LDS read-modify-writes per lane).
+// U_k and D_k are final rows of earlier levels and each group's blocks are contiguous, so
+// the loads of group t + P - 1 are issued while group t computes, into P rotating register
+// sets; the group descriptors arrive 64 at a time, one per lane, broadcast by readlane.
+template <int NT, int P>
 __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ sub_lvl,
                                                    const int32_t* __restrict__ lvl_ptr,
                                                    const int32_t* __restrict__ rows,
                                                    const int32_t* __restrict__ lrowptr,
-                                                   const int32_t* __restrict__ kent_ptr,
-                                                   const int32_t* __restrict__ kent_ik,
-                                                   const int32_t* __restrict__ kent_dk,
-                                                   const int32_t* __restrict__ kent_tptr,
-                                                   const int32_t* __restrict__ tri_kj,
-                                                   const int32_t* __restrict__ tri_ij,
+                                                   const int32_t* __restrict__ fgrp_ptr,
+                                                   const int4* __restrict__ fgrp,
+                                                   const int32_t* __restrict__ umap,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int maxrow) {
@@ -75,14 +132,29 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ s
   const int ent = lane < 49 ? lane : 48;  // lanes 49..63 shadow entry 48 and never store
   const bool owner = lane < 49;
   const int rr = ent / 7, cc = ent % 7;
-  double* row = lds + (size_t)wave * maxrow * 49;
+  const int qb = lane / 7, qc = lane % 7;  // group lanes: block and column
+  const bool qlane = lane < 7 * kFacHalf;
+  const int voff_u = qlane ? 8 * (49 * qb + qc) : kOutside;
+  const int voff_d = owner ? 8 * ent : kOutside;
+  double* row = lds + (size_t)wave * (maxrow * 49 + 56);
+  double* dsc = row + (size_t)maxrow * 49;  // D_k of the current pivot
   const int L0 = sub_lvl[s], L1 = sub_lvl[s + 1];
   for (int L = L0; L < L1; ++L) {
     const int r1 = lvl_ptr[L + 1];
     for (int q = lvl_ptr[L] + wave; q < r1; q += NW) {
-      const int i = rows[q];
-      const int rb = lrowptr[i], nbe = (lrowptr[i + 1] - rb) * 49;
+      // row metadata is uniform across the wavefront: keep it in scalar registers
+      const int i = __builtin_amdgcn_readfirstlane(rows[q]);
+      const int rb = __builtin_amdgcn_readfirstlane(lrowptr[i]);
+      const int nbe = (__builtin_amdgcn_readfirstlane(lrowptr[i + 1]) - rb) * 49;
       const size_t gb = (size_t)rb * 49;
+      const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
+      const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
+      // c0 holds groups [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
+      // P - 1 groups, so group t and group t + P - 1 loaded with it always share c0
+      constexpr int kStride = 64 - (P - 1);
+      auto chunk = [&](int t) { return fgrp[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
+      int cb = 0;
+      int4 c0 = chunk(0), c1 = chunk(kStride);
       // stage the row: all loads of a round issued before its LDS writes
       for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
         double tmp[8];
@@ -98,93 +170,65 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ s
         }
       }
       wave_lds_sync();
-      const int kb = kent_ptr[i], nk = kent_ptr[i + 1] - kb;
-      for (int kbase = 0; kbase < nk; kbase += 64) {
-        const int lk = kb + kbase + lane;
-        const bool hk = kbase + lane < nk;
-        const int mik = hk ? kent_ik[lk] - rb : 0, mdk = hk ? kent_dk[lk] : 0;
-        const int mt0 = hk ? kent_tptr[lk] : 0, mt1 = hk ? kent_tptr[lk + 1] : 0;
-        const int cnt = nk - kbase < 64 ? nk - kbase : 64;
-        // prefetch of pivot e: D_k column, pair indices (lane-indexed), first kTri U_kj columns
-        auto prefetch = [&](int e, double d[7], int& ikj, int& iij, double b[kTri][7]) {
-          const size_t pdk = (size_t)__builtin_amdgcn_readlane(mdk, e) * 49;
-          const int tb = __builtin_amdgcn_readlane(mt0, e), te = __builtin_amdgcn_readlane(mt1, e);
-#pragma unroll
-          for (int m = 0; m < 7; ++m) d[m] = fac[pdk + 7 * m + cc];
-          const int lt = tb + lane < te ? tb + lane : (te > tb ? tb : 0);  // no pairs: any valid index
-          ikj = tri_kj[lt];
-          iij = tri_ij[lt] - rb;
-#pragma unroll
-          for (int u = 0; u < kTri; ++u) {
-            const int src = u < te - tb ? u : 0;
-            const size_t pkj = (size_t)__builtin_amdgcn_readlane(ikj, src) * 49;
-#pragma unroll
-            for (int m = 0; m < 7; ++m) b[u][m] = fac[pkj + 7 * m + cc];
-          }
-        };
-        double dk[7], b0[kTri][7];
-        int ikj, iij;
-        prefetch(0, dk, ikj, iij, b0);
-        for (int e = 0; e < cnt; ++e) {
-          const int pik = __builtin_amdgcn_readlane(mik, e) * 49;
-          const int tb = __builtin_amdgcn_readlane(mt0, e), te = __builtin_amdgcn_readlane(mt1, e);
-          const int nt = te - tb;
-          double arow[7];
-#pragma unroll
-          for (int m = 0; m < 7; ++m) arow[m] = row[pik + 7 * rr + m];
+      double lrow[7][7];  // L_ik of the current pivot, all entries in every lane
+      auto consume = [&](const FacGroup& G, const FacDesc& F) {
+        const int pik = F.flags >> 6;
+        if (F.flags & 1) {  // first group of the pivot: L_ik = A_ik D_k
+          if (owner) dsc[ent] = G.d;
+          wave_lds_sync();
           double l = 0.0;
 #pragma unroll
-          for (int m = 0; m < 7; ++m) l += arow[m] * dk[m];                    // L_ik = A_ik D_k
+          for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
           wave_lds_sync();
-          if (owner) row[pik + ent] = l;
+          if (owner) row[pik * 49 + ent] = l;
           wave_lds_sync();
-          double lrow[7];
 #pragma unroll
-          for (int m = 0; m < 7; ++m) lrow[m] = row[pik + 7 * rr + m];
-          double dn[7], bn[kTri][7];
-          int nkj = 0, nij = 0;
-          if (e + 1 < cnt) prefetch(e + 1, dn, nkj, nij, bn);
+          for (int r = 0; r < 7; ++r)
 #pragma unroll
-          for (int u = 0; u < kTri; ++u) {                                         // A_ij -= L_ik U_kj
-            double upd = 0.0;
+            for (int m = 0; m < 7; ++m) lrow[r][m] = row[pik * 49 + 7 * r + m];
+        }
 #pragma unroll
-            for (int m = 0; m < 7; ++m) upd += lrow[m] * b0[u][m];
-            const int pij = __builtin_amdgcn_readlane(iij, u < nt ? u : 0) * 49;
-            if (owner && u < nt) row[pij + ent] -= upd;
+        for (int h = 0; h < 2; ++h) {  // A_ij -= L_ik U_kj, column qc
+          double acc[7];
+#pragma unroll
+          for (int r = 0; r < 7; ++r) {
+            acc[r] = 0.0;
+#pragma unroll
+            for (int m = 0; m < 7; ++m) acc[r] += lrow[r][m] * G.u[h][m];
           }
-          for (int t0 = kTri; t0 < nt; t0 += kTri) {   // remaining pairs of this pivot
+          if (qlane && G.pos[h] > 0) {
+            double* a = row + (G.pos[h] - 1) * 49 + qc;
 #pragma unroll
-            for (int u = 0; u < kTri; ++u) {
-              const int t = t0 + u < nt ? t0 + u : t0;
-              const size_t pkj = (size_t)(t < 64 ? __builtin_amdgcn_readlane(ikj, t) : tri_kj[tb + t]) * 49;
-#pragma unroll
-              for (int m = 0; m < 7; ++m) b0[u][m] = fac[pkj + 7 * m + cc];
-            }
-#pragma unroll
-            for (int u = 0; u < kTri; ++u) {
-              const int t = t0 + u < nt ? t0 + u : t0;
-              double upd = 0.0;
-#pragma unroll
-              for (int m = 0; m < 7; ++m) upd += lrow[m] * b0[u][m];
-              const int pij = (t < 64 ? __builtin_amdgcn_readlane(iij, t) : tri_ij[tb + t] - rb) * 49;
-              if (owner && t0 + u < nt) row[pij + ent] -= upd;
-            }
+            for (int r = 0; r < 7; ++r) a[7 * r] -= acc[r];
           }
-          wave_lds_sync();
-          if (e + 1 < cnt) {
+        }
+        wave_lds_sync();
+      };
+      if (ng > 0) {
+        FacGroup buf[P];
 #pragma unroll
-            for (int m = 0; m < 7; ++m) dk[m] = dn[m];
+        for (int k = 0; k + 1 < P; ++k) {
+          const int u = k < ng ? k : ng - 1;
+          fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, umap, voff_u, voff_d, lane);
+        }
+        for (int t0 = 0; t0 < ng; t0 += P) {
 #pragma unroll
-            for (int u = 0; u < kTri; ++u)
-#pragma unroll
-              for (int m = 0; m < 7; ++m) b0[u][m] = bn[u][m];
-            ikj = nkj;
-            iij = nij;
+          for (int k = 0; k < P; ++k) {
+            const int t = t0 + k;
+            if (t < ng && t + P - 1 - cb == 64) {  // the chunk at cb + kStride starts at group t
+              c0 = c1;
+              cb += kStride;
+              c1 = chunk(cb + kStride);
+            }
+            const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
+            fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, umap, voff_u, voff_d,
+                           lane);
+            if (t < ng) consume(buf[k], desc_get(c0, t - cb));
           }
         }
       }
       // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
-      const int pd = (ldiag[i] - rb) * 49;
+      const int pd = (__builtin_amdgcn_readfirstlane(ldiag[i]) - rb) * 49;
       double M = row[pd + ent];
       if (owner) udiag[49 * (size_t)i + ent] = M;
       double Iv = (rr == cc) ? 1.0 : 0.0;
@@ -193,12 +237,12 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ s
         double colv[7];
 #pragma unroll
         for (int m = 0; m < 7; ++m) colv[m] = __shfl(M, m * 7 + p, 64);
-        int piv = p;
+        int pr = p;
         double best = fabs(colv[p]);
         for (int m = p + 1; m < 7; ++m)
-          if (fabs(colv[m]) > best) { best = fabs(colv[m]); piv = m; }
+          if (fabs(colv[m]) > best) { best = fabs(colv[m]); pr = m; }
         if (!(best > 0.0) || !isfinite(best)) bad = true;
-        const int srow = (rr == p) ? piv : (rr == piv ? p : rr);
+        const int srow = (rr == p) ? pr : (rr == pr ? p : rr);
         M = __shfl(M, srow * 7 + cc, 64);
         Iv = __shfl(Iv, srow * 7 + cc, 64);
         const double pv = __shfl(M, p * 7 + p, 64);
@@ -234,7 +278,7 @@ hipError_t launch_pc_setup(fsi_solver* s) {
   hipLaunchKernelGGL(k_ilu_gather, dim3(nblk(s->NB * 49, 256)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
                      s->fac);
   // up to four row-staging wavefronts per workgroup, as many as the longest row allows
-  const size_t per_wave = (size_t)s->max_rowblk * 49 * sizeof(double);
+  const size_t per_wave = ((size_t)s->max_rowblk * 49 + 56) * sizeof(double);
   const int waves = (int)std::min<size_t>(4, (160 * 1024) / per_wave);
   if (waves < 1) return hipErrorInvalidConfiguration;  // a row too long to stage in LDS
   const size_t lds = per_wave * waves;
@@ -243,12 +287,13 @@ hipError_t launch_pc_setup(fsi_solver* s) {
     if (e != hipSuccess) return e;
     FSI_PROF_LAUNCH(s, "ilu_factor",
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_sub_lvl, s->fwd_lvl_ptr,
-                                       s->fwd_rows, s->lrowptr, s->kent_ptr, s->kent_ik, s->kent_dk, s->kent_tptr,
-                                       s->tri_kj, s->tri_ij, s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk));
+                                       s->fwd_rows, s->lrowptr, s->fgrp_ptr, s->fgrp, s->umap, s->ldiag, s->fac,
+                                       s->udiag, s->flags, s->max_rowblk));
     return hipSuccess;
   };
-  hipError_t e = waves >= 4 ? go(k_ilu_factor<256>, 256) : waves == 3 ? go(k_ilu_factor<192>, 192)
-                 : waves == 2 ? go(k_ilu_factor<128>, 128) : go(k_ilu_factor<64>, 64);
+  constexpr int P = kFacDepth;
+  hipError_t e = waves >= 4 ? go(k_ilu_factor<256, P>, 256) : waves == 3 ? go(k_ilu_factor<192, P>, 192)
+                 : waves == 2 ? go(k_ilu_factor<128, P>, 128) : go(k_ilu_factor<64, P>, 64);
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -317,22 +362,6 @@ __device__ __forceinline__ TaskMeta chunk_get(const TaskChunk& c, int l) {
   return TaskMeta{__builtin_amdgcn_readlane(c.m.x, l), __builtin_amdgcn_readlane(c.m.y, l),
                   __builtin_amdgcn_readlane(c.m.z, l), __builtin_amdgcn_readlane(c.m.w, l),
                   __builtin_amdgcn_readlane(c.a.x, l), __builtin_amdgcn_readlane(c.a.y, l)};
-}
-
-// Raw buffer loads: a resource spans exactly the bytes a task may read, and the hardware
-// returns 0 for a lane whose offset (vector offset + immediate) falls outside it, without
-// touching memory.  Padding lanes use an offset that is always outside.
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-constexpr int kBufFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
-constexpr int kOutside = (int)0x80000000u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t span_rsrc(const void* p, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, bytes, kBufFlags);
-}
-
-__device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int voff) {
-  const u32x2_t v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0);
-  return __hiloint2double((int)v.y, (int)v.x);
 }
 
 template <int MB>

@@ -290,11 +290,8 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
   h.bwd_lvl_ptr.assign(1, 0);
   h.bwd_rows.clear();
   h.kent_ptr.assign(1, 0);
-  h.kent_ik.clear();
-  h.kent_dk.clear();
-  h.kent_tptr.assign(1, 0);
-  h.tri_kj.clear();
-  h.tri_ij.clear();
+  h.piv.clear();
+  h.umap.clear();
 
   std::vector<int32_t> owners_of(V);
   std::vector<std::vector<int32_t>> members(ns);
@@ -409,25 +406,24 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
     };
     emit(lf, nf, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl);
     emit(lb, nbk, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl);
-    // factorization work lists: for each row i, its L blocks (ascending k) with the
-    // position of D_k and the pairs (U_kj, A_ij) for j > k present in row i
+    // factorization work lists: for each row i, its L blocks (ascending k) as pivots
+    // {position of A_ik in row i, D_k, length of U_k, offset of U_k's map}; the map gives,
+    // for every block U_kj of row k, 1 + the position of A_ij in row i, or 0 when (i, j)
+    // is not in the pattern
     for (int i = 0; i < m; ++i) {
       const int32_t* ci0 = &h.lcol[rowb(i)];
       const int32_t* ci1 = &h.lcol[0] + rowe(i);
       for (int p = rowb(i); p < h.ldiag[base + i]; ++p) {
-        int k = h.lcol[p] - base;
-        h.kent_ik.push_back(p);
-        h.kent_dk.push_back(h.ldiag[base + k]);
-        for (int q = h.ldiag[base + k] + 1; q < rowe(k); ++q) {
-          const int32_t* f = std::lower_bound(ci0, ci1, h.lcol[q]);
-          if (f != ci1 && *f == h.lcol[q]) {
-            h.tri_kj.push_back(q);
-            h.tri_ij.push_back((int32_t)(f - &h.lcol[0]));
-          }
+        const int k = h.lcol[p] - base;
+        const int u0 = h.ldiag[base + k] + 1, u1 = rowe(k);
+        h.piv.insert(h.piv.end(), {p - rowb(i), h.ldiag[base + k], u1 - u0, (int32_t)h.umap.size()});
+        const int32_t* f = ci0;
+        for (int q = u0; q < u1; ++q) {  // both column lists ascend: one merge walk
+          f = std::lower_bound(f, ci1, h.lcol[q]);
+          h.umap.push_back(f != ci1 && *f == h.lcol[q] ? (int32_t)(f - ci0) + 1 : 0);
         }
-        h.kent_tptr.push_back((int32_t)h.tri_kj.size());
       }
-      h.kent_ptr.push_back((int32_t)h.kent_ik.size());
+      h.kent_ptr.push_back((int32_t)(h.piv.size() / 4));
     }
     // LDS slots for the sweeps: y_k (forward) or x_k (backward) is live from its own level
     // to the level of its last reader; slots are handed out greedily in level order and
