@@ -3,8 +3,9 @@
 Workload: the seeded synthetic bifurcating compliant tree of depth 3 (8 outlets, radius
 ratio 0.79, branch angles 25-45 deg, one-lattice-cell wall), about 203k vertices and 1.37M
 active unknowns, pulsatile inflow 30 + 15 sin(2 pi t / 0.8) cm/s, traction-free planar outlets,
-dt = 1e-3 s, 64 restricted additive Schwarz subdomains with overlap 1 and block ILU(l)
-subdomain solves (l = 3 by default: lower fill levels stall GMRES(30) on this wall).
+dt = 1e-3 s, 256 restricted additive Schwarz subdomains (one per compute unit) with overlap
+1 and block ILU(l) subdomain solves (l = 3 by default: lower fill levels stall GMRES(30) on
+this wall with 64 subdomains, and are slower with 256).
 
 A step is one whole Newton-Krylov-Schwarz solve (residuals, exact Jacobians, Schwarz
 setups, GMRES iterations, line searches) through the library's C ABI.  Before the warmup
@@ -87,19 +88,20 @@ def spmv_bytes(s) -> int:
     return s.nnzb * (49 * 8 + 4) + 4 * (s.V + 1) + 2 * 7 * s.V * 8
 
 
-def cpu_baseline(counts: dict, ilu_level: int, V_work: int) -> dict:
+def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int) -> dict:
     """The oracle (1 host core) timed on a bounded sample and scaled to the workload.
 
-    Sample: the depth-1 tree (about 26k vertices, 8 subdomains of the same size as the
-    workload's), one call each of FuncEval, JacEval and PCSetUp and 8 GMRES iterations;
-    the per-call times are combined with the GPU run's per-step call counts and scaled by
-    the vertex ratio (every phase is linear in the mesh size at fixed subdomain size).
+    Sample: the depth-1 tree (about 26k vertices, cut into subdomains of the workload's
+    size), one call each of FuncEval, JacEval and PCSetUp and 8 GMRES iterations; the
+    per-call times are combined with the GPU run's per-step call counts and scaled by the
+    vertex ratio (every phase is linear in the mesh size at fixed subdomain size).
     """
     import oracle as O
     O.build()
     m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     ph = W.physics_config1()
-    o = O.Oracle(m, ph, dict(nsub=8, overlap=1, ilu_level=ilu_level, gmres_rtol=0.0, gmres_maxit=8))
+    ns = max(1, round(nsub_work * m.nverts / V_work))
+    o = O.Oracle(m, ph, dict(nsub=ns, overlap=1, ilu_level=ilu_level, gmres_rtol=0.0, gmres_maxit=8))
     g = W.dirichlet_values(m, 30.0)
     y0 = W.perturbed_state(m, np.zeros(m.n), seed=1)
     o.set_step(1e-3, 1e-3, np.zeros(m.n), g)
@@ -120,7 +122,7 @@ def cpu_baseline(counts: dict, ilu_level: int, V_work: int) -> dict:
                 counts["gmres_iters"] * t_it)
     scale = V_work / m.nverts
     return {"value": per_step * scale, "unit": "s/step", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle phases on the depth-1 tree ({m.nverts} vertices, 8 subdomains, ILU({ilu_level})): "
+            "sample": (f"oracle phases on the depth-1 tree ({m.nverts} vertices, {ns} subdomains, ILU({ilu_level})): "
                        f"FuncEval {t_fe:.3f}s, JacEval {t_je:.3f}s, PCSetUp {t_ps:.3f}s, GMRES iter {t_it:.4f}s; "
                        f"combined with the GPU run's per-step counts {counts} and scaled by {scale:.2f} "
                        f"(vertex ratio)"),
@@ -143,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--depth", type=int, default=3)
-    ap.add_argument("--nsub", type=int, default=64)
+    ap.add_argument("--nsub", type=int, default=256)
     ap.add_argument("--ilu", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -261,7 +263,7 @@ def main():
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts)
+        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub)
     print(json.dumps(out), flush=True)
     s.close()
 

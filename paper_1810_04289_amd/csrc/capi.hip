@@ -408,39 +408,17 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     const int mb = s->sweep_mb;
     auto tasks = [&](bool bwd, const std::vector<int32_t>& sub_lvl, const std::vector<int32_t>& lvl_ptr,
                      const std::vector<int32_t>& rows, const std::vector<int32_t>& qslot, int32_t** wtask_d,
-                     int4** task_d, int2** aux_d) {
-      std::vector<int32_t> wtask(h.ns * kSweepWaves + 1, 0);
-      std::vector<int4> task;
-      std::vector<int2> aux;
-      task.reserve(rows.size());
-      aux.reserve(rows.size());
-      for (int sd = 0; sd < h.ns; ++sd)
-        for (int w = 0; w < kSweepWaves; ++w) {
-          for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L)
-            for (int q = lvl_ptr[L] + w; q < lvl_ptr[L + 1]; q += kSweepWaves) {
-              const int i = rows[q];
-              const int g = h.lglob[i] | (h.lowned[i] ? (int)0x80000000u : 0);
-              const int b0 = bwd ? h.ldiag[i] + 1 : h.lrowptr[i], b1 = bwd ? h.lrowptr[i + 1] : h.ldiag[i];
-              const int nc = std::max(1, (b1 - b0 + mb - 1) / mb);
-              for (int c = 0; c < nc; ++c) {
-                // backward: chunks from the row's end, so the one next to D_i comes last
-                const int k = bwd ? nc - 1 - c : c;
-                const int f = b0 + k * mb, l = std::min(b1, f + mb);
-                const int flags = (c > 0 ? (1 << 28) : 0) | (c + 1 < nc ? (1 << 29) : 0);
-                task.push_back(make_int4(i, g, f, l));
-                aux.push_back(make_int2(qslot[q], (L - sub_lvl[sd]) | flags));
-              }
-            }
-          wtask[sd * kSweepWaves + w + 1] = (int32_t)task.size();
-        }
-      *wtask_d = upload(s, wtask);
-      *task_d = upload(s, task);
-      *aux_d = upload(s, aux);
+                     int4** task_d, int4** aux_d, int32_t** nphase_d) {
+      SweepTasks st = build_sweep_tasks(h, bwd, sub_lvl, lvl_ptr, rows, qslot, mb);
+      *wtask_d = upload(s, st.wtask);
+      *task_d = upload(s, st.task);
+      *aux_d = upload(s, st.aux);
+      *nphase_d = upload(s, st.nphase);
     };
     tasks(false, h.fwd_sub_lvl, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_qslot, &s->fwd_wtask, &s->fwd_task,
-          &s->fwd_task_aux);
+          &s->fwd_task_aux, &s->fwd_nphase);
     tasks(true, h.bwd_sub_lvl, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, &s->bwd_wtask, &s->bwd_task,
-          &s->bwd_task_aux);
+          &s->bwd_task_aux, &s->bwd_nphase);
     std::vector<int32_t> lbyte(h.lslot.size());
     for (size_t p = 0; p < lbyte.size(); ++p) lbyte[p] = h.lslot[p] >= 0 ? 56 * h.lslot[p] : 0;
     s->lslot = upload(s, lbyte);

@@ -69,6 +69,23 @@ struct HostSetup {
 std::string build_topology(HostSetup& h);
 std::string build_subdomains(HostSetup& h, const fsi_opts& o);
 
+// Task lists of one triangular sweep.  Each subdomain's levels are phases, walked by its
+// kSweepWaves wavefronts with a workgroup barrier between phases; a level's rows go to the
+// wavefronts round-robin.  Wavefront w of subdomain s runs tasks
+// [wtask[s*kSweepWaves + w], wtask[s*kSweepWaves + w + 1]).  A task covers at most mb
+// blocks: task = {row, global vertex (bit 31 = owned), first, last}, its blocks
+// [first, last) (forward: L; backward: U; when a backward row takes several tasks, the one
+// next to D_i comes last); aux = {own LDS slot or -1, phase, flags, 0}.
+// nphase[s] = phases of subdomain s.
+enum : int { kTaskCont = 1, kTaskMore = 2 };
+struct SweepTasks {
+  std::vector<int32_t> wtask, nphase;
+  std::vector<int4> task, aux;
+};
+SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int32_t>& sub_lvl,
+                             const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows,
+                             const std::vector<int32_t>& qslot, int mb);
+
 struct ProfEntry {
   std::string name;
   hipEvent_t a, b;
@@ -103,16 +120,11 @@ struct fsi_solver {
   uint8_t* lowned = nullptr;
   int32_t *fwd_sub_lvl = nullptr, *fwd_lvl_ptr = nullptr, *fwd_rows = nullptr;
   int32_t *bwd_sub_lvl = nullptr, *bwd_lvl_ptr = nullptr, *bwd_rows = nullptr;
-  // sweep task lists: the rows of a subdomain's level go to its kSweepWaves wavefronts
-  // round-robin; wavefront w of subdomain s takes tasks [wtask[s*kSweepWaves + w],
-  // wtask[s*kSweepWaves + w + 1]) in level order.  A row is one task per sweep_mb of its
-  // strict blocks.  task = {row, global vertex (bit 31 = owned), first, last}: the task's
-  // blocks [first, last) (forward: L; backward: U, the chunk next to D_i last);
-  // task_aux = {own LDS slot or -1, level | continues-row bit 28 | row-continues bit 29}.
+  // sweep task lists (see SweepTasks); sweep_mb: blocks per task
   int sweep_mb = 0;
-  int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr;
+  int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr, *fwd_nphase = nullptr, *bwd_nphase = nullptr;
   int4 *fwd_task = nullptr, *bwd_task = nullptr;
-  int2 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
+  int4 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
   int32_t* lslot = nullptr;  // per block: LDS byte offset (56 * slot) of its column row's slot
   // factorization groups: row i's are fgrp[fgrp_ptr[i] .. fgrp_ptr[i+1]), for each pivot k
   // (ascending) U_k in runs of up to 2*kFacHalf blocks (one run if U_k is empty):

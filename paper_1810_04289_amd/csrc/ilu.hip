@@ -340,28 +340,24 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 struct TaskMeta {  // one task, uniform across the wavefront
-  int row, vtx, first, last, slot, lvf;  // lvf: level | kTaskCont | kTaskMore
+  int row, vtx, first, last, slot, phase, flags, unused;
 };
 
 struct TaskChunk {  // lane j: task base + j
-  int4 m;
-  int2 a;
+  int4 m, a;
 };
 
-__device__ __forceinline__ TaskChunk load_chunk(const int4* __restrict__ task, const int2* __restrict__ aux, int t,
+__device__ __forceinline__ TaskChunk load_chunk(const int4* __restrict__ task, const int4* __restrict__ aux, int t,
                                                 int te, int lane) {
   const int q = t + lane < te ? t + lane : te - 1;
   return TaskChunk{task[q], aux[q]};
 }
 
-constexpr int kTaskLevel = (1 << 28) - 1;
-constexpr int kTaskCont = 1 << 28;  // continues the previous task's row
-constexpr int kTaskMore = 1 << 29;  // the row continues in the next task
-
 __device__ __forceinline__ TaskMeta chunk_get(const TaskChunk& c, int l) {
   return TaskMeta{__builtin_amdgcn_readlane(c.m.x, l), __builtin_amdgcn_readlane(c.m.y, l),
                   __builtin_amdgcn_readlane(c.m.z, l), __builtin_amdgcn_readlane(c.m.w, l),
-                  __builtin_amdgcn_readlane(c.a.x, l), __builtin_amdgcn_readlane(c.a.y, l)};
+                  __builtin_amdgcn_readlane(c.a.x, l), __builtin_amdgcn_readlane(c.a.y, l),
+                  __builtin_amdgcn_readlane(c.a.z, l), __builtin_amdgcn_readlane(c.a.w, l)};
 }
 
 template <int MB>
@@ -407,7 +403,7 @@ __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& 
                                          int c) {
   const int nb = T.last - T.first;
   const int cc = c < 7 ? c : 6;
-  if (!(T.lvf & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+  if (!(T.flags & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
   // groups of eight blocks: the LDS reads of a group are issued together; blocks beyond
   // the range contribute A = 0 times a finite slot value.  Block b goes to acc[b % 4]:
   // four independent FMA chains.
@@ -422,7 +418,7 @@ __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& 
       for (int u = 0; u < 8 && g + u < MB; ++u) acc[u & 3] = fma(P.A[g + u], yv[u], acc[u & 3]);
     }
   }
-  if (T.lvf & kTaskMore) return;
+  if (T.flags & kTaskMore) return;
   // sum_c of row r of all blocks times the column values
   const double sum = sum8((acc[0] + acc[1]) + (acc[2] + acc[3]));
   double out;
@@ -442,10 +438,10 @@ __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& 
 }
 
 template <int BWD, int MB, int D>
-__global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* __restrict__ sub_lvl,
+__global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* __restrict__ nphase,
                                                                const int32_t* __restrict__ wtask,
                                                                const int4* __restrict__ task,
-                                                               const int2* __restrict__ aux,
+                                                               const int4* __restrict__ aux,
                                                                const int32_t* __restrict__ lslot,
                                                                const double* __restrict__ fac,
                                                                const double* __restrict__ v, double* yl,
@@ -460,12 +456,12 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   const int e = 7 * (r < 7 ? r : 6) + (c < 7 ? c : 6);   // block entry of the lane
   const int voff = (r < 7 && c < 7) ? 8 * e : kOutside;
   const char* ybuf_c = (const char*)ybuf + 8 * (c < 7 ? c : 6);
-  const int nL = sub_lvl[s + 1] - sub_lvl[s];
+  const int nL = nphase[s];
   // slots are read before their first write only through blocks with A = 0: keep them finite
   for (int t = threadIdx.x; t < 7 * nslots; t += 64 * kSweepWaves) ybuf[t] = 0.0;
   __syncthreads();
   const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
-  int cur = 0;  // level barriers passed
+  int cur = 0;  // phase barriers passed
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (te > tb) {
     // c0 holds tasks [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
@@ -494,8 +490,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
         task_load<BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
         if (t < te) {
           const TaskMeta T = chunk_get(c0, t - cb);
-          const int level = T.lvf & kTaskLevel;
-          while (cur < level) {
+          while (cur < T.phase) {
             lds_barrier();
             ++cur;
           }
@@ -504,7 +499,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
       }
     }
   }
-  while (cur < nL) {  // every wavefront passes the same number of barriers
+  while (cur < nL) {  // every wavefront passes the same number of barriers (one per phase)
     lds_barrier();
     ++cur;
   }
@@ -525,11 +520,11 @@ static hipError_t launch_sweeps(fsi_solver* s, const double* v, double* z) {
   }
   FSI_PROF_LAUNCH(s, "ilu_fwd",
                   hipLaunchKernelGGL((k_ilu_sweep<0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
-                                     s->fwd_sub_lvl, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, s->fac,
+                                     s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, s->fac,
                                      v, s->ylocal, z, s->h.nslots));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
                   hipLaunchKernelGGL((k_ilu_sweep<1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
-                                     s->bwd_sub_lvl, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, s->fac,
+                                     s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, s->fac,
                                      v, s->ylocal, z, s->h.nslots));
   return hipGetLastError();
 }

@@ -476,3 +476,55 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
 }
 
 }  // namespace fsi
+
+namespace fsi {
+
+SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int32_t>& sub_lvl,
+                             const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows,
+                             const std::vector<int32_t>& qslot, int mb) {
+  constexpr int W = kSweepWaves;
+  SweepTasks st;
+  st.wtask.assign((size_t)h.ns * W + 1, 0);
+  st.nphase.assign(h.ns, 0);
+  std::vector<std::vector<int4>> wt(W), wa(W);
+  auto blocks = [&](int i, int& b0, int& b1) {
+    b0 = bwd ? h.ldiag[i] + 1 : h.lrowptr[i];
+    b1 = bwd ? h.lrowptr[i + 1] : h.ldiag[i];
+  };
+  // blocks [f, l) of row rows[q] on wavefront w, as tasks of at most mb blocks; the final
+  // task, which in the backward sweep is the one starting at f, finishes the row
+  auto emit = [&](int w, int q, int f, int l, int phase) {
+    const int i = rows[q];
+    const int g = h.lglob[i] | (h.lowned[i] ? (int)0x80000000u : 0);
+    const int nc = std::max(1, (l - f + mb - 1) / mb);
+    for (int c = 0; c < nc; ++c) {
+      const int k = bwd ? nc - 1 - c : c;
+      const int cf = f + k * mb, cl = std::min(l, cf + mb);
+      const int flags = (c > 0 ? kTaskCont : 0) | (c + 1 < nc ? kTaskMore : 0);
+      wt[w].push_back(make_int4(i, g, cf, cl));
+      wa[w].push_back(make_int4(c + 1 < nc ? -1 : qslot[q], phase, flags, 0));
+    }
+  };
+  for (int sd = 0; sd < h.ns; ++sd) {
+    for (int w = 0; w < W; ++w) {
+      wt[w].clear();
+      wa[w].clear();
+    }
+    int ph = 0;
+    for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L, ++ph)
+      for (int q = lvl_ptr[L]; q < lvl_ptr[L + 1]; ++q) {
+        int b0, b1;
+        blocks(rows[q], b0, b1);
+        emit((q - lvl_ptr[L]) % W, q, b0, b1, ph);
+      }
+    st.nphase[sd] = ph;
+    for (int w = 0; w < W; ++w) {
+      st.task.insert(st.task.end(), wt[w].begin(), wt[w].end());
+      st.aux.insert(st.aux.end(), wa[w].begin(), wa[w].end());
+      st.wtask[(size_t)sd * W + w + 1] = (int32_t)st.task.size();
+    }
+  }
+  return st;
+}
+
+}  // namespace fsi

@@ -487,7 +487,7 @@ def test_full_size_residual_parity(tree, fsi_mod):
     m = tree
     g = W.dirichlet_values(m, 30.0)
     y0 = np.zeros(m.n)
-    opts = dict(nsub=64, overlap=1, ilu_level=3)
+    opts = dict(nsub=256, overlap=1, ilu_level=3)
     P = Pair(fsi_mod, m, opts, y0, g)
     y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=9))
     F = P.g.vec()
@@ -519,7 +519,7 @@ def test_full_size_residual_parity(tree, fsi_mod):
     # factorization identity LU = A on sampled rows of one subdomain, with GPU factors
     P.g.pc_setup()
     pc = P.g.pc_get()
-    s = 17
+    s = 137
     v0, v1 = pc["sub_ptr"][s], pc["sub_ptr"][s + 1]
     b0 = pc["blk_ptr"][s]
     lrp = pc["lrowptr"][v0 + s:v1 + s + 1]
@@ -569,12 +569,12 @@ def test_full_size_residual_parity(tree, fsi_mod):
 
 @pytest.mark.parametrize("rigid", [True, False])
 def test_tree_schwarz_parity_bench_like(fsi_mod, rigid):
-    """Bench-like Schwarz configuration at oracle-checkable size: the depth-1 tree, eight
-    subdomains of the benchmark's size, ILU(3) (rows longer than one sweep task are split
-    into several); GPU and oracle factor the same matrix."""
+    """Bench-like Schwarz configuration at oracle-checkable size: the depth-1 tree cut into
+    subdomains of the benchmark's size (33), ILU(3) (rows longer than one sweep task are
+    split into several); GPU and oracle factor the same matrix."""
     m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     g = W.dirichlet_values(m, 30.0)
-    opts = dict(nsub=8, overlap=1, ilu_level=3)
+    opts = dict(nsub=33, overlap=1, ilu_level=3)
     P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m) if rigid else None)
     y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
     P.o.jacobian(y)
