@@ -37,16 +37,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def sweep_bytes(s) -> dict:
-    """Algorithmic HBM bytes of one launch of each triangular sweep of the Schwarz solve.
+def sweep_bytes(s, precision: int = 0) -> dict:
+    """Algorithmic HBM bytes of one launch of each triangular sweep of the Schwarz solve,
+    with factor entries of vb bytes (8 FP64, 4 FP32, 2 BF16) and local values of yb bytes
+    (8 FP64, else 4).
 
-    forward  (y = L^-1 R v): strict-L blocks (392 B each) and their column slot (4 B), a
-             24 B task record per local row, the gathered input (7 doubles per local row)
-             and y written (7 doubles per local row);
-    backward (x = U^-1 y): strict-U blocks and the inverted diagonal of every row (392 B
+    forward  (y = L^-1 R v): strict-L blocks (49 vb each) and their column slot (4 B), a
+             24 B task record per local row, the gathered FP64 input (7 doubles per local
+             row) and y written (7 yb per local row);
+    backward (x = U^-1 y): strict-U blocks and the inverted diagonal of every row (49 vb
              each), the U column slots, the task records, y read, and the owned rows of z
              written (7 doubles per vertex).
     """
+    vb = {0: 8, 1: 4, 2: 2}[precision]
+    yb = 8 if precision == 0 else 4
     pc = s.pc_get(factors=False)
     ns = len(pc["sub_nowned"])
     rp = pc["lrowptr"].astype(np.int64)
@@ -62,14 +66,14 @@ def sweep_bytes(s) -> dict:
     NB = len(col)
     R = len(pc["sub_verts"])
     nU = NB - R - nL
-    fwd = nL * (392 + 4) + 24 * R + 2 * 56 * R
-    bwd = (nU + R) * 392 + 4 * nU + 24 * R + 56 * R + 56 * s.V
+    fwd = nL * (49 * vb + 4) + 24 * R + 56 * R + 7 * yb * R
+    bwd = (nU + R) * 49 * vb + 4 * nU + 24 * R + 7 * yb * R + 56 * s.V
     return dict(ilu_fwd=fwd, ilu_bwd=bwd, local_blocks=NB, local_rows=R, l_blocks=nL, u_blocks=nU)
 
 
-def stored_traffic(kernel: str):
+def stored_traffic(kernel: str, precision: int):
     """HBM bytes per launch measured with rocprofv3 counters, if the profile on record was
-    taken with the current sweep source; None otherwise."""
+    taken with the current sweep source and the same sweep precision; None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3.json")
     try:
@@ -77,7 +81,7 @@ def stored_traffic(kernel: str):
     except (OSError, ValueError):
         return None
     src = open(os.path.join(ROOT, "paper_1810_04289_amd", "csrc", "ilu.hip"), "rb").read()
-    if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest() or rec.get("precision", 0) != precision:
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -88,7 +92,7 @@ def spmv_bytes(s) -> int:
     return s.nnzb * (49 * 8 + 4) + 4 * (s.V + 1) + 2 * 7 * s.V * 8
 
 
-def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int) -> dict:
+def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1) -> dict:
     """The oracle (1 host core) timed on a bounded sample and scaled to the workload.
 
     Sample: the depth-1 tree (about 26k vertices, cut into subdomains of the workload's
@@ -101,7 +105,7 @@ def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int) -> d
     m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     ph = W.physics_config1()
     ns = max(1, round(nsub_work * m.nverts / V_work))
-    o = O.Oracle(m, ph, dict(nsub=ns, overlap=1, ilu_level=ilu_level, gmres_rtol=0.0, gmres_maxit=8))
+    o = O.Oracle(m, ph, dict(nsub=ns, overlap=overlap, ilu_level=ilu_level, gmres_rtol=0.0, gmres_maxit=8))
     g = W.dirichlet_values(m, 30.0)
     y0 = W.perturbed_state(m, np.zeros(m.n), seed=1)
     o.set_step(1e-3, 1e-3, np.zeros(m.n), g)
@@ -148,6 +152,10 @@ def main():
     ap.add_argument("--nsub", type=int, default=256)
     ap.add_argument("--ilu", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--overlap", type=int, default=1)
+    ap.add_argument("--jac-lag", type=int, default=1, help="Newton iterations per Jacobian and Schwarz setup")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB three times "
@@ -167,8 +175,9 @@ def main():
     t0 = time.perf_counter()
     mesh = W.tree_mesh(depth=args.depth, h=W.TREE_H[args.depth])
     ph = W.physics_config1()
-    opts = dict(nsub=args.nsub, overlap=1, ilu_level=args.ilu, gmres_restart=30, gmres_maxit=600,
-                gmres_rtol=1e-3, newton_rtol=1e-6, newton_maxit=20)
+    opts = dict(nsub=args.nsub, overlap=args.overlap, ilu_level=args.ilu, jac_lag=args.jac_lag, gmres_restart=30,
+                gmres_maxit=600,
+                gmres_rtol=1e-3, newton_rtol=1e-6, newton_maxit=20, precision=args.precision)
     s = fsi.Solver(mesh, ph, opts)
     log(f"[bench] mesh V={mesh.nverts} E={mesh.ntets} n={s.n} nnzb={s.nnzb} setup {time.perf_counter() - t0:.1f}s")
 
@@ -222,7 +231,7 @@ def main():
         kernels[name] = {"total_ms": round(ms, 3), "count": cnt, "avg_us": round(1e3 * ms / cnt, 2) if cnt else None}
     s.prof_enable(False)
 
-    sw = sweep_bytes(s)
+    sw = sweep_bytes(s, args.precision)
     dom = max(("ilu_fwd", "ilu_bwd"), key=lambda k: kernels[k]["total_ms"])
     t_dom = kernels[dom]["avg_us"]
     achieved = sw[dom] / (t_dom * 1e-6) / 1e9 if t_dom else None
@@ -235,7 +244,8 @@ def main():
     LI = float(np.sum([x["linear_iters"] for x in stats]) / max(1, np.sum([x["newton_iters"] for x in stats])))
     counts = {
         "funceval": float(np.mean([x["newton_iters"] + 1 + x["line_search_cuts"] for x in stats])),
-        "jaceval": NI, "pcsetup": NI,
+        "jaceval": float(np.mean([-(-x["newton_iters"] // args.jac_lag) for x in stats])),
+        "pcsetup": float(np.mean([-(-x["newton_iters"] // args.jac_lag) for x in stats])),
         "gmres_iters": float(np.mean([x["linear_iters"] for x in stats])),
     }
     phases = {k: float(np.mean([x[k] for x in stats])) for k in
@@ -243,27 +253,30 @@ def main():
     out = {
         "metric": METRIC, "value": round(sec_per_step, 5), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * sec_per_step, 2), "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {0: "f64", 1: "f64 (f32 Schwarz sweeps)", 2: "f64 (bf16 factors, f32 Schwarz sweeps)"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": f"bifurcating compliant tree depth {args.depth}, {mesh.nverts} vertices, "
-                               f"{mesh.ntets} tets, {s.n} unknowns, dt {dt}, {args.nsub} RAS subdomains overlap 1, "
-                               f"ILU({args.ilu}), GMRES(30) rtol 1e-3, Newton rtol 1e-6",
+                               f"{mesh.ntets} tets, {s.n} unknowns, dt {dt}, {args.nsub} RAS subdomains overlap {args.overlap}, "
+                               f"ILU({args.ilu}), GMRES(30) rtol 1e-3, Newton rtol 1e-6"
+                               + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps"}[args.precision],
                    "nverts": mesh.nverts, "ntets": mesh.ntets, "n": s.n, "nnzb": s.nnzb, "nsub": args.nsub,
-                   "ilu_level": args.ilu, "dt": dt, "local_blocks": sw["local_blocks"],
+                   "ilu_level": args.ilu, "overlap": args.overlap, "jac_lag": args.jac_lag, "dt": dt, "local_blocks": sw["local_blocks"],
                    "local_rows": sw["local_rows"]},
         "NI": NI, "LI": round(LI, 2), "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
-                     "traffic": stored_traffic(dom), "bytes_per_launch": sw[dom], "avg_us": t_dom,
+                     "traffic": stored_traffic(dom, args.precision), "bytes_per_launch": sw[dom], "avg_us": t_dom,
                      "other_sweep": {"kernel": other, "bytes_per_launch": sw[other], "avg_us": t_other,
                                      "achieved": round(sw[other] / (t_other * 1e-6) / 1e9, 1) if t_other else None,
-                                     "traffic": stored_traffic(other)}},
+                                     "traffic": stored_traffic(other, args.precision)}},
         "spmv": {"achieved_GBs": round(spmv_gbs, 1) if spmv_gbs else None, "bytes": sb,
                  "frac": round(spmv_gbs / HBM_PEAK, 4) if spmv_gbs else None},
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub)
+        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap)
     print(json.dumps(out), flush=True)
     s.close()
 

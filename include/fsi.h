@@ -82,8 +82,15 @@ typedef struct {
   int32_t newton_maxit, jac_lag;
   double ls_c;              /* Armijo constant of the backtracking line search */
   int32_t ls_max_halvings;
-  int32_t precision;        /* 0 = FP64 everywhere */
+  int32_t precision;        /* FSI_PREC_*: arithmetic of the Schwarz triangular sweeps */
 } fsi_opts;
+
+/* Precision of the preconditioner application (the mixed-precision variant of §3's
+ * Schwarz preconditioner).  The factorization is FP64 in every mode; FP32 and BF16 store
+ * a rounded copy of the factors (round to nearest, ties to even) and run both triangular
+ * sweeps in FP32 arithmetic, including accumulation.  The input v and output z of
+ * fsi_pc_apply stay FP64, as do residuals, GMRES and the Newton update. */
+enum { FSI_PREC_FP64 = 0, FSI_PREC_FP32 = 1, FSI_PREC_BF16 = 2 };
 
 typedef struct {
   int32_t iters, restarts, converged, pad;

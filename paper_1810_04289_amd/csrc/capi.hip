@@ -97,6 +97,7 @@ fsi_status pc_setup_impl(fsi_solver* s) {
   }
   clear_flags(s);
   hip_ok(s, launch_pc_setup(s), "pc_setup");
+  hip_ok(s, launch_fac_round(s), "factor rounding");
   if (read_flag(s, 1)) {
     s->err = "zero pivot in a subdomain factorization";
     return FSI_ERR_ZERO_PIVOT;
@@ -420,7 +421,9 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     tasks(true, h.bwd_sub_lvl, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, &s->bwd_wtask, &s->bwd_task,
           &s->bwd_task_aux, &s->bwd_nphase);
     std::vector<int32_t> lbyte(h.lslot.size());
-    for (size_t p = 0; p < lbyte.size(); ++p) lbyte[p] = h.lslot[p] >= 0 ? 56 * h.lslot[p] : 0;
+    // a slot holds 7 values of the sweep arithmetic type (FP64, or FP32 for rounded factors)
+    const int slot_bytes = 7 * (s->opts.precision == FSI_PREC_FP64 ? 8 : 4);
+    for (size_t p = 0; p < lbyte.size(); ++p) lbyte[p] = h.lslot[p] >= 0 ? slot_bytes * h.lslot[p] : 0;
     s->lslot = upload(s, lbyte);
   }
   {
@@ -445,6 +448,8 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->umap = upload(s, h.umap);
   s->sub_row_off = upload(s, h.sub_row_off);
   s->fac = dalloc<double>(s, (size_t)s->NB * 49);
+  if (s->opts.precision == FSI_PREC_FP32) s->facs = dalloc<float>(s, (size_t)s->NB * 49);
+  if (s->opts.precision == FSI_PREC_BF16) s->facs = dalloc<uint16_t>(s, (size_t)s->NB * 49);
   s->udiag = dalloc<double>(s, (size_t)s->R * 49);
   s->ylocal = dalloc<double>(s, (size_t)s->R * 7);
   const int mrs = s->opts.gmres_restart;
@@ -520,7 +525,7 @@ fsi_status fsi_create(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* 
     return FSI_ERR_ARG;
   if (o->nsub <= 0 || o->nsub > m->nverts || o->overlap < 0 || o->ilu_level < 0 || o->ilu_level > 8 ||
       o->gmres_restart <= 0 || o->gmres_restart > kMaxRestart || o->gmres_maxit <= 0 || o->ordering != 0 ||
-      o->precision != 0 || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
+      o->precision < FSI_PREC_FP64 || o->precision > FSI_PREC_BF16 || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
     return FSI_ERR_ARG;
   fsi_solver* s = new (std::nothrow) fsi_solver();
   if (!s) return FSI_ERR_OOM;

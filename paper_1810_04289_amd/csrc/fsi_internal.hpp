@@ -133,6 +133,7 @@ struct fsi_solver {
   int4* fgrp = nullptr;
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
+  void* facs = nullptr;  // FP32 or BF16 copy of fac for the sweeps (precision 1 or 2)
   // Krylov / Newton work vectors
   double *Vb = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr;
   double *partial = nullptr, *hdev = nullptr, *yvdev = nullptr;
@@ -154,6 +155,7 @@ hipError_t launch_impose(fsi_solver* s, double* y);
 hipError_t launch_spmv(fsi_solver* s, const double* x, double* y);
 hipError_t launch_pc_setup(fsi_solver* s);
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
+hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);

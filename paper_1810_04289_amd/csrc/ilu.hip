@@ -317,6 +317,37 @@ hipError_t launch_pc_setup(fsi_solver* s) {
 // only for the set about to be used.  A row longer than MB blocks is split into consecutive
 // tasks of at most MB blocks that carry their partial sums in registers; only the last one
 // finishes the row (the backward sweep takes the chunk next to D_i last).
+// Factor storage of the sweeps: FP64 (computed in FP64), or the FP64 factors rounded to
+// FP32 or BF16 with FP32 arithmetic.  Value<S>::C is the arithmetic type.
+struct bf16_t {
+  uint16_t bits;
+};
+template <typename S>
+struct Value;
+template <>
+struct Value<double> {
+  using C = double;
+  __device__ static double load(__amdgpu_buffer_rsrc_t r, int voff) { return span_load_f64(r, voff); }
+};
+template <>
+struct Value<float> {
+  using C = float;
+  __device__ static float load(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+  }
+};
+template <>
+struct Value<bf16_t> {
+  using C = float;
+  __device__ static float load(__amdgpu_buffer_rsrc_t r, int voff) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, 0, 0) << 16);
+  }
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
@@ -326,7 +357,8 @@ __device__ __forceinline__ double dpp_mov(double x) {
 
 // sum over the eight lanes of an aligned group of eight (xor 1, xor 2, then the mirror
 // lane of the other half)
-__device__ __forceinline__ double sum8(double v) {
+template <typename C>
+__device__ __forceinline__ C sum8(C v) {
   v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_mov<0x141>(v);  // row_half_mirror
@@ -360,27 +392,30 @@ __device__ __forceinline__ TaskMeta chunk_get(const TaskChunk& c, int l) {
                   __builtin_amdgcn_readlane(c.a.z, l), __builtin_amdgcn_readlane(c.a.w, l)};
 }
 
-template <int MB>
+template <typename C, int MB>
 struct TaskData {
-  double A[MB];   // entry (r, c) of the task's blocks; 0 beyond its range and on padding lanes
-  int ls;         // lane b < MB: LDS byte offset of the column row of block b (0 beyond the range)
-  double base;    // forward: v of the vertex (component r); backward: y_i (component r)
-  double D;       // backward: entry (r, c) of D_i (0 on padding lanes)
+  C A[MB];   // entry (r, c) of the task's blocks; 0 beyond its range and on padding lanes
+  int ls;    // lane b < MB: LDS byte offset of the column row of block b (0 beyond the range)
+  C base;    // forward: v of the vertex (component r); backward: y_i (component r)
+  C D;       // backward: entry (r, c) of D_i (0 on padding lanes)
 };
 
-// voff: 8 * (7r + c) on the 49 block lanes, kOutside on padding lanes
-template <int BWD, int MB>
-__device__ __forceinline__ void task_load(TaskData<MB>& P, const TaskMeta& T, const int32_t* __restrict__ lslot,
-                                          const double* __restrict__ fac, const double* __restrict__ v,
-                                          const double* yl, int lane, int voff, int r) {
+// voff: sizeof(S) * (7r + c) on the 49 block lanes, kOutside on padding lanes
+template <typename S, int BWD, int MB>
+__device__ __forceinline__ void task_load(TaskData<typename Value<S>::C, MB>& P, const TaskMeta& T,
+                                          const int32_t* __restrict__ lslot, const S* __restrict__ fac,
+                                          const double* __restrict__ v, const typename Value<S>::C* yl, int lane,
+                                          int voff, int r) {
+  using C = typename Value<S>::C;
+  constexpr int BB = 49 * (int)sizeof(S);  // bytes per block
   const int first = T.first;
   const int nb = T.last - first;
   // one resource per group of eight blocks keeps every block offset in the immediate field
 #pragma unroll
   for (int g = 0; g < MB; g += 8) {
-    const __amdgpu_buffer_rsrc_t ra = span_rsrc(fac + 49 * (size_t)(first + g), nb > g ? 392 * (nb - g) : 0);
+    const __amdgpu_buffer_rsrc_t ra = span_rsrc(fac + 49 * (size_t)(first + g), nb > g ? BB * (nb - g) : 0);
 #pragma unroll
-    for (int u = 0; u < 8 && g + u < MB; ++u) P.A[g + u] = span_load_f64(ra, voff + 392 * u);
+    for (int u = 0; u < 8 && g + u < MB; ++u) P.A[g + u] = Value<S>::load(ra, voff + BB * u);
   }
   const __amdgpu_buffer_rsrc_t rl = span_rsrc(lslot + first, 4 * nb);
   P.ls = (int)__builtin_amdgcn_raw_buffer_load_b32(rl, 4 * lane, 0, 0);
@@ -389,80 +424,82 @@ __device__ __forceinline__ void task_load(TaskData<MB>& P, const TaskMeta& T, co
     P.base = yl[7 * (size_t)T.row + rv];
     // D_i precedes the row's first U block; chunks other than the last read a U block
     // here, which they do not use
-    P.D = span_load_f64(span_rsrc(fac + 49 * (size_t)(T.first - 1), 392), voff);
+    P.D = Value<S>::load(span_rsrc(fac + 49 * (size_t)(T.first - 1), BB), voff);
   } else {
-    P.base = v[7 * (size_t)(T.vtx & 0x7fffffff) + rv];
+    P.base = (C)v[7 * (size_t)(T.vtx & 0x7fffffff) + rv];
   }
 }
 
-// ybuf_c: this lane's component column of the LDS slots (byte address of ybuf + 8c);
+// ybuf_c: this lane's component column of the LDS slots (byte address of ybuf + c * sizeof(C));
 // acc: the row's partial sums, carried from task to task while a row continues
-template <int BWD, int MB>
-__device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<MB>& P, const char* ybuf_c, double* ybuf,
-                                         double* scr, double* yl, double* __restrict__ z, double (&acc)[4], int r,
-                                         int c) {
+template <typename C, int BWD, int MB>
+__device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<C, MB>& P, const char* ybuf_c, C* ybuf,
+                                         C* scr, C* yl, double* __restrict__ z, C (&acc)[4], int r, int c) {
   const int nb = T.last - T.first;
   const int cc = c < 7 ? c : 6;
-  if (!(T.flags & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = 0.0;
+  if (!(T.flags & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = (C)0;
   // groups of eight blocks: the LDS reads of a group are issued together; blocks beyond
   // the range contribute A = 0 times a finite slot value.  Block b goes to acc[b % 4]:
   // four independent FMA chains.
 #pragma unroll
   for (int g = 0; g < MB; g += 8) {
     if (g < nb) {
-      double yv[8];
+      C yv[8];
 #pragma unroll
       for (int u = 0; u < 8 && g + u < MB; ++u)
-        yv[u] = *(const double*)(ybuf_c + __builtin_amdgcn_readlane(P.ls, g + u));
+        yv[u] = *(const C*)(ybuf_c + __builtin_amdgcn_readlane(P.ls, g + u));
 #pragma unroll
       for (int u = 0; u < 8 && g + u < MB; ++u) acc[u & 3] = fma(P.A[g + u], yv[u], acc[u & 3]);
     }
   }
   if (T.flags & kTaskMore) return;
   // sum_c of row r of all blocks times the column values
-  const double sum = sum8((acc[0] + acc[1]) + (acc[2] + acc[3]));
-  double out;
+  const C sum = sum8<C>((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  C out;
   if (!BWD) {
     out = P.base - sum;                                   // y_i = b_i - sum_k L_ik y_k
     if (c == 0 && r < 7) yl[7 * (size_t)T.row + r] = out;
   } else {
-    const double t = P.base - sum;                        // y_i - sum_j U_ij x_j
+    const C t = P.base - sum;                             // y_i - sum_j U_ij x_j
     if (c == 0 && r < 7) scr[r] = t;
     wave_lds_sync();
-    const double tc = scr[cc];
+    const C tc = scr[cc];
     wave_lds_sync();
-    out = sum8(P.D * tc);                                 // x_i = D_i (...)
-    if (c == 0 && r < 7 && T.vtx < 0) z[7 * (size_t)(T.vtx & 0x7fffffff) + r] = out;
+    out = sum8<C>(P.D * tc);                              // x_i = D_i (...)
+    if (c == 0 && r < 7 && T.vtx < 0) z[7 * (size_t)(T.vtx & 0x7fffffff) + r] = (double)out;
   }
   if (T.slot >= 0 && c == 0 && r < 7) ybuf[7 * T.slot + r] = out;
 }
 
-template <int BWD, int MB, int D>
+template <typename S, int BWD, int MB, int D>
 __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* __restrict__ nphase,
                                                                const int32_t* __restrict__ wtask,
                                                                const int4* __restrict__ task,
                                                                const int4* __restrict__ aux,
                                                                const int32_t* __restrict__ lslot,
-                                                               const double* __restrict__ fac,
-                                                               const double* __restrict__ v, double* yl,
-                                                               double* __restrict__ z, int nslots) {
-  extern __shared__ double lds[];
-  double* ybuf = lds;                          // [nslots][7]
+                                                               const S* __restrict__ fac,
+                                                               const double* __restrict__ v,
+                                                               typename Value<S>::C* yl, double* __restrict__ z,
+                                                               int nslots) {
+  using C = typename Value<S>::C;
+  extern __shared__ double lds_d[];
+  C* lds = (C*)lds_d;
+  C* ybuf = lds;                               // [nslots][7]
   const int s = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double* scr = lds + 7 * (size_t)nslots + 8 * wave;   // [8] per wavefront
+  C* scr = lds + 7 * (size_t)nslots + 8 * wave;   // [8] per wavefront
   const int r = lane >> 3, c = lane & 7;
   const int e = 7 * (r < 7 ? r : 6) + (c < 7 ? c : 6);   // block entry of the lane
-  const int voff = (r < 7 && c < 7) ? 8 * e : kOutside;
-  const char* ybuf_c = (const char*)ybuf + 8 * (c < 7 ? c : 6);
+  const int voff = (r < 7 && c < 7) ? (int)sizeof(S) * e : kOutside;
+  const char* ybuf_c = (const char*)ybuf + sizeof(C) * (c < 7 ? c : 6);
   const int nL = nphase[s];
   // slots are read before their first write only through blocks with A = 0: keep them finite
-  for (int t = threadIdx.x; t < 7 * nslots; t += 64 * kSweepWaves) ybuf[t] = 0.0;
+  for (int t = threadIdx.x; t < 7 * nslots; t += 64 * kSweepWaves) ybuf[t] = (C)0;
   __syncthreads();
   const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
   int cur = 0;  // phase barriers passed
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  C acc[4] = {(C)0, (C)0, (C)0, (C)0};
   if (te > tb) {
     // c0 holds tasks [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
     // D - 1 tasks, so task t and the task t + D - 1 loaded with it always share c0 and c1
@@ -471,11 +508,11 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
     int cb = tb;
     TaskChunk c0 = load_chunk(task, aux, cb, te, lane);
     TaskChunk c1 = load_chunk(task, aux, cb + kStride, te, lane);
-    TaskData<MB> buf[D];
+    TaskData<C, MB> buf[D];
 #pragma unroll
     for (int k = 0; k + 1 < D; ++k) {
       const int u = tb + k < te ? tb + k : te - 1;
-      task_load<BWD, MB>(buf[k], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
+      task_load<S, BWD, MB>(buf[k], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
     }
     for (int t0 = tb; t0 < te; t0 += D) {
 #pragma unroll
@@ -487,14 +524,14 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
           c1 = load_chunk(task, aux, cb + kStride, te, lane);
         }
         const int u = t + D - 1 < te ? t + D - 1 : te - 1;
-        task_load<BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
+        task_load<S, BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
         if (t < te) {
           const TaskMeta T = chunk_get(c0, t - cb);
           while (cur < T.phase) {
             lds_barrier();
             ++cur;
           }
-          task_run<BWD, MB>(T, buf[k], ybuf_c, ybuf, scr, yl, z, acc, r, c);
+          task_run<C, BWD, MB>(T, buf[k], ybuf_c, ybuf, scr, yl, z, acc, r, c);
         }
       }
     }
@@ -505,28 +542,39 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   }
 }
 
-template <int MB, int D>
-static hipError_t launch_sweeps(fsi_solver* s, const double* v, double* z) {
+template <typename S, int MB, int D>
+static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, double* z) {
+  using C = typename Value<S>::C;
   constexpr int NT = 64 * kSweepWaves;
-  const size_t lds = (size_t)s->h.nslots * 7 * sizeof(double) + kSweepWaves * 8 * sizeof(double);
+  const size_t lds = ((size_t)s->h.nslots * 7 + kSweepWaves * 8) * sizeof(C);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ilu_sweep<0, MB, D>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_ilu_sweep<S, 0, MB, D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_ilu_sweep<1, MB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      e = hipFuncSetAttribute((const void*)k_ilu_sweep<S, 1, MB, D>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     if (e != hipSuccess) return e;
   }
+  C* yl = (C*)s->ylocal;
   FSI_PROF_LAUNCH(s, "ilu_fwd",
-                  hipLaunchKernelGGL((k_ilu_sweep<0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
-                                     s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, s->fac,
-                                     v, s->ylocal, z, s->h.nslots));
+                  hipLaunchKernelGGL((k_ilu_sweep<S, 0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
+                                     s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, facs, v, yl,
+                                     z, s->h.nslots));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
-                  hipLaunchKernelGGL((k_ilu_sweep<1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
-                                     s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, s->fac,
-                                     v, s->ylocal, z, s->h.nslots));
+                  hipLaunchKernelGGL((k_ilu_sweep<S, 1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
+                                     s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, facs, v, yl,
+                                     z, s->h.nslots));
   return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_sweeps_mb(fsi_solver* s, const S* facs, const double* v, double* z) {
+  switch (s->sweep_mb) {
+    case 16: return launch_sweeps<S, 16, 4>(s, facs, v, z);
+    case 24: return launch_sweeps<S, 24, 3>(s, facs, v, z);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Blocks per sweep task (rows are split into tasks of at most this many blocks) and the
@@ -535,12 +583,38 @@ static hipError_t launch_sweeps(fsi_solver* s, const double* v, double* z) {
 int sweep_task_blocks(int longest_part) { return longest_part <= 16 ? 16 : 24; }
 
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
-  switch (s->sweep_mb) {
-    case 16: return launch_sweeps<16, 4>(s, v, z);
-    case 24: return launch_sweeps<24, 3>(s, v, z);
-    case 32: return launch_sweeps<32, 2>(s, v, z);
+  switch (s->opts.precision) {
+    case FSI_PREC_FP64: return launch_sweeps_mb<double>(s, s->fac, v, z);
+    case FSI_PREC_FP32: return launch_sweeps_mb<float>(s, (const float*)s->facs, v, z);
+    case FSI_PREC_BF16: return launch_sweeps_mb<bf16_t>(s, (const bf16_t*)s->facs, v, z);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Sweep copy of the factors: FP64 rounded to nearest FP32, or to nearest-even BF16.
+__global__ void __launch_bounds__(256) k_fac_round_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void __launch_bounds__(256) k_fac_round_bf16(int64_t n, const double* __restrict__ a,
+                                                        uint16_t* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t u = __float_as_uint((float)a[i]);
+  // round to nearest even on the 16 dropped bits; NaN stays NaN
+  const uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+  b[i] = (uint16_t)(r >> 16);
+}
+
+hipError_t launch_fac_round(fsi_solver* s) {
+  const int64_t n = s->NB * 49;
+  if (n == 0 || s->opts.precision == FSI_PREC_FP64) return hipSuccess;
+  if (s->opts.precision == FSI_PREC_FP32)
+    hipLaunchKernelGGL(k_fac_round_f32, dim3(nblk(n, 256)), dim3(256), 0, s->stream, n, s->fac, (float*)s->facs);
+  else
+    hipLaunchKernelGGL(k_fac_round_bf16, dim3(nblk(n, 256)), dim3(256), 0, s->stream, n, s->fac,
+                       (uint16_t*)s->facs);
+  return hipGetLastError();
 }
 
 }  // namespace fsi

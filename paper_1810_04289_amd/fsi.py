@@ -76,6 +76,10 @@ def _todict(st) -> dict:
 _lib = None
 
 
+# precision of the Schwarz triangular sweeps (fsi_opts.precision)
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+
+
 def load_library(path: str = LIB_PATH):
     """Load libfsi.so and declare its signatures.  Raises if the library is missing."""
     global _lib
