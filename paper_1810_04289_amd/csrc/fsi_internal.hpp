@@ -70,8 +70,8 @@ std::string build_topology(HostSetup& h);
 std::string build_subdomains(HostSetup& h, const fsi_opts& o);
 
 // Task lists of one triangular sweep.  Each subdomain's levels are phases, walked by its
-// kSweepWaves wavefronts with a workgroup barrier between phases; a level's rows go to the
-// wavefronts round-robin.  Wavefront w of subdomain s runs tasks
+// kSweepWaves wavefronts with a workgroup barrier between phases; the rows go to the
+// wavefronts round-robin in schedule order.  Wavefront w of subdomain s runs tasks
 // [wtask[s*kSweepWaves + w], wtask[s*kSweepWaves + w + 1]).  A task covers at most mb
 // blocks: task = {row, global vertex (bit 31 = owned), first, last}, its blocks
 // [first, last) (forward: L; backward: U; when a backward row takes several tasks, the one

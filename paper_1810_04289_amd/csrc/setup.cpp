@@ -510,12 +510,15 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
       wt[w].clear();
       wa[w].clear();
     }
-    int ph = 0;
+    // rows go to the wavefronts round-robin over the whole schedule, not per level: with
+    // about one row per level, consecutive levels then fall to different wavefronts, and
+    // each wavefront issues its next prefetch while the others work
+    int ph = 0, next = 0;
     for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L, ++ph)
       for (int q = lvl_ptr[L]; q < lvl_ptr[L + 1]; ++q) {
         int b0, b1;
         blocks(rows[q], b0, b1);
-        emit((q - lvl_ptr[L]) % W, q, b0, b1, ph);
+        emit(next++ % W, q, b0, b1, ph);
       }
     st.nphase[sd] = ph;
     for (int w = 0; w < W; ++w) {

@@ -69,7 +69,7 @@ def test_mixed_pc_apply_rigid_wall(fsi_mod):
         err[prec] = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     say(f"[mixed pc, rigid wall] rel. error vs FP64 oracle: FP64 {err[0]:.2e} FP32 {err[1]:.2e} BF16 {err[2]:.2e}")
     assert err[fsi.PREC_FP64] <= 1e-10
-    # measured about 30 u and 2 u (level chains of a few hundred rows); bounds of 1e3 u
+    # measured 1.5 u (FP32) and 0.5 u (BF16) on this case; bounds of 1e3 u
     assert err[fsi.PREC_FP32] <= 1e3 * U32
     assert err[fsi.PREC_BF16] <= 1e3 * U16 and err[fsi.PREC_BF16] > err[fsi.PREC_FP32]
 
