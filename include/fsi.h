@@ -168,6 +168,11 @@ fsi_status fsi_gmres(fsi_solver *s, const double *rhs /* dev, n */, double *x /*
  * result.  Error DIVERGED if the iteration limit is hit or the line search fails. */
 fsi_status fsi_newton_solve(fsi_solver *s, double *y, fsi_step_stats *st /* host, may be NULL */);
 
+/* Replace the Newton tolerances of fsi_opts (rtol >= 0, atol >= 0, not both 0) for the
+ * following solves.  A fixed absolute target (rtol = 0) lets solves from different initial
+ * guesses of one step be compared at equal accuracy. */
+fsi_status fsi_set_newton_tol(fsi_solver *s, double rtol, double atol);
+
 /* ---- introspection (host copies; for tests and diagnostics) ---- */
 /* vkind[nverts]: 0 fluid, 1 interface, 2 wall; rowkind[n]: 0 element, 1 Dirichlet,
  * 2 kinematic, 3 dummy; interface triangles from Algorithm 1 as [n_iface][3]. */

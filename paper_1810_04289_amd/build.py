@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfsi.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["setup.cpp", "assembly.hip", "linalg.hip", "ilu.hip", "capi.hip"]
+SOURCES = ["setup.cpp", "assembly.hip", "linalg.hip", "ilu.hip", "capi.hip", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

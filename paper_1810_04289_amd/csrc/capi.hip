@@ -710,6 +710,13 @@ fsi_status fsi_gmres(fsi_solver* s, const double* rhs, double* x, fsi_lin_stats*
   }, &a);
 }
 
+fsi_status fsi_set_newton_tol(fsi_solver* s, double rtol, double atol) {
+  if (!s || !(rtol >= 0.0) || !(atol >= 0.0) || (rtol == 0.0 && atol == 0.0)) return FSI_ERR_ARG;
+  s->opts.newton_rtol = rtol;
+  s->opts.newton_atol = atol;
+  return FSI_OK;
+}
+
 fsi_status fsi_newton_solve(fsi_solver* s, double* y, fsi_step_stats* st) {
   if (!s || !y || !s->has_step) return FSI_ERR_ARG;
   struct A {

@@ -22,7 +22,12 @@ SYMBOLS = ["fsi_create", "fsi_destroy", "fsi_sizes", "fsi_last_error", "fsi_set_
            "fsi_impose_dirichlet", "fsi_residual", "fsi_jacobian", "fsi_jacobian_get", "fsi_jacobian_set",
            "fsi_spmv",
            "fsi_pc_setup", "fsi_pc_apply", "fsi_gmres", "fsi_newton_solve", "fsi_topology_get",
-           "fsi_pc_sizes", "fsi_pc_get", "fsi_prof_enable", "fsi_prof_get"]
+           "fsi_pc_sizes", "fsi_pc_get", "fsi_prof_enable", "fsi_prof_get", "fsi_set_newton_tol"]
+# include/fsi_guess.h
+GUESS_SYMBOLS = ["fsi_mlp_create", "fsi_mlp_destroy", "fsi_mlp_last_error", "fsi_mlp_nparams", "fsi_mlp_set_params",
+                 "fsi_mlp_get_params", "fsi_mlp_forward", "fsi_mlp_loss_grad", "fsi_mlp_train_step",
+                 "fsi_mlp_set_scales", "fsi_guess_features", "fsi_guess_target", "fsi_guess_predict", "fsi_gemm_f32"]
+GUESS_NIN = 18
 
 
 class FsiError(RuntimeError):
@@ -89,7 +94,7 @@ def load_library(path: str = LIB_PATH):
         raise FileNotFoundError(f"{path} is missing: build it with `python __graft_entry__.py` "
                                 "or `python paper_1810_04289_amd/build.py`")
     L = C.CDLL(path)
-    vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+    vp, i32, i64, dbl, flt = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_float
     sig = {
         "fsi_create": [vp, vp, vp, vp, vp], "fsi_destroy": [vp], "fsi_sizes": [vp, vp, vp],
         "fsi_set_step": [vp, dbl, dbl, vp, vp, vp, vp], "fsi_impose_dirichlet": [vp, vp],
@@ -99,6 +104,14 @@ def load_library(path: str = LIB_PATH):
         "fsi_gmres": [vp, vp, vp, vp], "fsi_newton_solve": [vp, vp, vp],
         "fsi_topology_get": [vp, vp, vp, vp, vp], "fsi_pc_sizes": [vp, vp, vp, vp, vp],
         "fsi_pc_get": [vp] * 10, "fsi_prof_enable": [vp, i32], "fsi_prof_get": [vp, C.c_char_p, vp, vp],
+        "fsi_set_newton_tol": [vp, dbl, dbl],
+        "fsi_mlp_create": [i32, i32, i32, i32, i64, vp, vp], "fsi_mlp_destroy": [vp],
+        "fsi_mlp_set_params": [vp, vp], "fsi_mlp_get_params": [vp, vp, vp], "fsi_mlp_forward": [vp, vp, i64, vp],
+        "fsi_mlp_loss_grad": [vp, vp, vp, i64, vp],
+        "fsi_mlp_train_step": [vp, vp, vp, i64, flt, flt, flt, flt, vp], "fsi_mlp_set_scales": [vp, vp],
+        "fsi_guess_features": [vp, vp, vp, i64, vp, vp], "fsi_guess_target": [vp, vp, vp, vp, i64, vp],
+        "fsi_guess_predict": [vp, vp, vp, i64, vp, vp, vp],
+        "fsi_gemm_f32": [i32, i32, i32, flt, vp, i64, i64, vp, i64, i64, flt, vp, i64, vp],
     }
     for k, a in sig.items():
         f = getattr(L, k)
@@ -106,6 +119,10 @@ def load_library(path: str = LIB_PATH):
         f.restype = C.c_int
     L.fsi_last_error.argtypes = [vp]
     L.fsi_last_error.restype = C.c_char_p
+    L.fsi_mlp_last_error.argtypes = [vp]
+    L.fsi_mlp_last_error.restype = C.c_char_p
+    L.fsi_mlp_nparams.argtypes = [vp]
+    L.fsi_mlp_nparams.restype = C.c_int64
     _lib = L
     return L
 
@@ -227,6 +244,9 @@ class Solver:
         self._chk(load_library().fsi_gmres(self.h, _dptr(rhs), _dptr(x), C.byref(st)), "gmres")
         return _todict(st)
 
+    def set_newton_tol(self, rtol, atol):
+        self._chk(load_library().fsi_set_newton_tol(self.h, rtol, atol), "set_newton_tol")
+
     def newton_solve(self, y, check=True):
         st = StepStatsC()
         rc = load_library().fsi_newton_solve(self.h, _dptr(y), C.byref(st))
@@ -269,3 +289,121 @@ class Solver:
         ms, cnt = C.c_double(), C.c_int64()
         self._chk(load_library().fsi_prof_get(self.h, kernel.encode(), C.byref(ms), C.byref(cnt)), "prof_get")
         return ms.value, cnt.value
+
+
+def _fptr(t):
+    """Device pointer of a contiguous float32/float64 torch tensor on a GPU."""
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+class MLP:
+    """Node-wise perceptron of the learned Newton guess (include/fsi_guess.h)."""
+
+    def __init__(self, nin: int = GUESS_NIN, hidden: int = 128, nlayers: int = 4, nout: int = 7, nmax: int = 1):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        L = load_library()
+        h = C.c_void_p()
+        rc = L.fsi_mlp_create(nin, hidden, nlayers, nout, nmax, None, C.byref(h))
+        if rc:
+            raise FsiError(rc, "fsi_mlp_create")
+        self.h, self.nin, self.nout, self.nmax = h, nin, nout, nmax
+        self.nparams = int(L.fsi_mlp_nparams(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            load_library().fsi_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, what):
+        if rc:
+            raise FsiError(rc, f"{what}: {load_library().fsi_mlp_last_error(self.h).decode()}")
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparams
+        self._chk(load_library().fsi_mlp_set_params(self.h, p.ctypes.data), "set_params")
+
+    def get_params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        g = np.zeros(self.nparams, dtype=np.float32)
+        self._chk(load_library().fsi_mlp_get_params(self.h, p.ctypes.data, g.ctypes.data), "get_params")
+        return p, g
+
+    def forward(self, X):
+        n = X.shape[0]
+        Y = self.torch.empty((n, self.nout), dtype=self.torch.float32, device=self.device)
+        self._chk(load_library().fsi_mlp_forward(self.h, _fptr(X), n, _fptr(Y)), "forward")
+        return Y
+
+    def loss_grad(self, X, T):
+        loss = C.c_double()
+        self._chk(load_library().fsi_mlp_loss_grad(self.h, _fptr(X), _fptr(T), X.shape[0], C.byref(loss)),
+                  "loss_grad")
+        return loss.value
+
+    def train_step(self, X, T, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        loss = C.c_double()
+        self._chk(load_library().fsi_mlp_train_step(self.h, _fptr(X), _fptr(T), X.shape[0], lr, b1, b2, eps,
+                                                    C.byref(loss)), "train_step")
+        return loss.value
+
+    def set_scales(self, sc):
+        sc = np.ascontiguousarray(sc, dtype=np.float32)
+        assert sc.size == 21
+        self._chk(load_library().fsi_mlp_set_scales(self.h, sc.ctypes.data), "set_scales")
+
+    def features(self, y1, y2, tfeat):
+        V = y1.numel() // 7
+        X = self.torch.empty((V, GUESS_NIN), dtype=self.torch.float32, device=self.device)
+        tf = np.ascontiguousarray(tfeat, dtype=np.float32)
+        self._chk(load_library().fsi_guess_features(self.h, _fptr(y1), _fptr(y2), V, tf.ctypes.data, _fptr(X)),
+                  "features")
+        return X
+
+    def target(self, y, y1, y2):
+        V = y.numel() // 7
+        T = self.torch.empty((V, 7), dtype=self.torch.float32, device=self.device)
+        self._chk(load_library().fsi_guess_target(self.h, _fptr(y), _fptr(y1), _fptr(y2), V, _fptr(T)), "target")
+        return T
+
+    def predict(self, y1, y2, tfeat=None, Xwork=None, out=None):
+        """Guess for the next step: extrapolation corrected by the network (tfeat given),
+        or the extrapolation alone."""
+        V = y1.numel() // 7
+        g = out if out is not None else self.torch.empty_like(y1)
+        tf = None if tfeat is None else np.ascontiguousarray(tfeat, dtype=np.float32)
+        if tf is not None and Xwork is None:
+            Xwork = self.torch.empty((V, GUESS_NIN), dtype=self.torch.float32, device=self.device)
+        self._chk(load_library().fsi_guess_predict(self.h, _fptr(y1), _fptr(y2), V,
+                                                   None if tf is None else tf.ctypes.data,
+                                                   _fptr(Xwork) if tf is not None else None, _fptr(g)), "predict")
+        return g
+
+
+def gemm_f32(A, B, C_=None, alpha=1.0, beta=0.0, transA=False, transB=False):
+    """C = alpha op(A) op(B) + beta C on the matrix cores (FP32 torch tensors on the GPU)."""
+    import torch
+    M, K = (A.shape[1], A.shape[0]) if transA else A.shape
+    K2, N = (B.shape[1], B.shape[0]) if transB else B.shape
+    assert K == K2
+    if C_ is None:
+        C_ = torch.zeros((M, N), dtype=torch.float32, device=A.device)
+    sam, sak = (1, A.shape[1]) if transA else (A.shape[1], 1)
+    sbk, sbn = (1, B.shape[1]) if transB else (B.shape[1], 1)
+    rc = load_library().fsi_gemm_f32(M, N, K, alpha, _fptr(A), sam, sak, _fptr(B), sbk, sbn, beta, _fptr(C_),
+                                      C_.shape[1], None)
+    if rc:
+        raise FsiError(rc, "fsi_gemm_f32")
+    return C_

@@ -10,14 +10,19 @@ from paper_1810_04289_amd import fsi
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "fsi.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fsi_[a-z_]+)\s*\(", src)))
+def declared_symbols(header=None):
+    names = [header] if header else sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    out = set()
+    for h in names:
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        out |= set(re.findall(r"\b(fsi_[a-z_0-9]+)\s*\(", src))
+    return sorted(out)
 
 
 def test_header_and_binding_agree():
-    assert declared_symbols() == sorted(fsi.SYMBOLS)
+    assert declared_symbols("fsi.h") == sorted(fsi.SYMBOLS)
+    assert declared_symbols("fsi_guess.h") == sorted(fsi.GUESS_SYMBOLS)
 
 
 def test_library_exports_every_declared_symbol():

@@ -527,3 +527,60 @@ def test_manufactured_solution_second_order_velocity():
     errs = [mms_error(nc) for nc in (6, 9, 12)]
     rates = [math.log(errs[i][0] / errs[i + 1][0]) / math.log(errs[i][1] / errs[i + 1][1]) for i in range(2)]
     assert rates[1] > rates[0] - 0.05 and rates[1] > 1.6, (errs, rates)
+
+
+# ------------------------------------------------------------------------------------------
+# learned Newton guess: the FP64 perceptron oracle (oracle/mlp.py)
+def test_mlp_gradient_matches_central_differences():
+    from oracle import mlp
+    dims = mlp.layer_dims(5, 6, 3, 2)
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(mlp.nparams(dims)) * 0.5
+    X = rng.standard_normal((7, 5))
+    T = rng.standard_normal((7, 2))
+    _, g = mlp.loss_grad(p, dims, X, T)
+    h = 1e-6
+    fd = np.empty_like(p)
+    for i in range(p.size):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (mlp.loss_grad(p + e, dims, X, T)[0] - mlp.loss_grad(p - e, dims, X, T)[0]) / (2 * h)
+    assert np.max(np.abs(fd - g)) <= 1e-8 * max(1.0, np.max(np.abs(g)))
+
+
+def test_mlp_single_linear_layer_closed_form():
+    # one layer, no activation: Y = X W + b, d loss / dW = 2/(n m) X^T (Y - T), db = column sums
+    from oracle import mlp
+    dims = mlp.layer_dims(4, 9, 1, 3)
+    rng = np.random.default_rng(12)
+    p = rng.standard_normal(mlp.nparams(dims))
+    X = rng.standard_normal((10, 4))
+    T = rng.standard_normal((10, 3))
+    W, b = p[:12].reshape(4, 3), p[12:]
+    R = X @ W + b - T
+    loss, g = mlp.loss_grad(p, dims, X, T)
+    assert abs(loss - np.mean(R ** 2)) <= 1e-14 * np.mean(R ** 2)
+    assert np.allclose(g[:12], (2.0 / 30) * (X.T @ R).ravel(), rtol=1e-13, atol=0)
+    assert np.allclose(g[12:], (2.0 / 30) * R.sum(axis=0), rtol=1e-13, atol=0)
+
+
+def test_adam_first_step_closed_form():
+    # after one step the bias-corrected moments are g and g^2: p1 = p0 - lr g / (|g| + eps)
+    from oracle import mlp
+    rng = np.random.default_rng(13)
+    p0, g = rng.standard_normal(20), rng.standard_normal(20)
+    p1, m, v = mlp.adam_step(p0, g, np.zeros(20), np.zeros(20), 1, lr=0.01, eps=1e-8)
+    assert np.allclose(p1, p0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_guess_target_round_trip():
+    # guess(y1, y2, target(y, y1, y2)) = y: the network output is a scaled correction of the
+    # linear extrapolation
+    from oracle import mlp
+    rng = np.random.default_rng(14)
+    y, y1, y2 = (rng.standard_normal(7 * 9) for _ in range(3))
+    s = rng.uniform(0.5, 2.0, 21)
+    T = mlp.target(y, y1, y2, s)
+    assert np.allclose(mlp.guess(y1, y2, T, s), y, rtol=1e-13, atol=1e-13)
+    X = mlp.features(y1, y2, s, [0.1, 0.2, 0.3, 0.4])
+    assert np.allclose(X[:, 0:7] * s[0:7], y1.reshape(-1, 7)) and np.allclose(X[:, 14:18], [0.1, 0.2, 0.3, 0.4])
