@@ -4,16 +4,21 @@
  * it by the nonlinear residual; the paper starts from the previous step's solution.  This
  * interface provides a better start without touching that test: a node-wise multilayer
  * perceptron, trained on the solver's own time steps, corrects the linear extrapolation
- *     g = 2 y_{n-1} - y_{n-2} + s_o (*) MLP(x),
- * where x are per-vertex features of y_{n-1}, y_{n-2} and the inflow phase, s_o are output
- * scales and (*) is the componentwise product.  Without a trained network the
- * extrapolation alone is the guess.  A Newton solve reaches the same residual tolerance
- * from any guess, so the guess affects only the cost of the step.
+ *     g = 2 y_{n-1} - y_{n-2} + gain (*) sigma (*) MLP(x),
+ * where x are per-vertex features of y_{n-1}, y_{n-2} and the inflow phase, (*) is the
+ * componentwise product over the 7 components of a vertex, gain a per-component switch
+ * (or weight) of the correction, and sigma the size of the last step's change:
+ *     sigma[c] = max(sqrt((1/V) sum_i (y_{n-1} - y_{n-2})[i][c]^2), floor[c]).
+ * Without a trained network the extrapolation alone is the guess.  A Newton solve reaches
+ * the same residual tolerance from any guess, so the guess affects only the cost of the
+ * step.
  *
  * Conventions: FP32 network, FP64 state vectors [V][7] as in fsi.h; device pointers are
  * the caller's and stay valid until the call returns; work runs on the stream given at
- * create time and calls return after it finished.  Errors are status codes, with a
- * message from fsi_mlp_last_error. */
+ * create time and calls return after it finished.  A call on zero rows (n = 0 or V = 0)
+ * does nothing and accepts NULL arrays.  Errors are status codes (FSI_ERR_ARG for bad
+ * arguments, FSI_ERR_HIP for a failed launch or copy), with a message from
+ * fsi_mlp_last_error. */
 #ifndef FSI_GUESS_H
 #define FSI_GUESS_H
 
@@ -27,7 +32,7 @@ extern "C" {
 
 typedef struct fsi_mlp fsi_mlp;
 
-/* features per vertex: y1 / s (7), (y1 - y2) / s_d (7), 4 inflow-phase features */
+/* features per vertex: y1 / s (7), (y1 - y2) / sigma (7), 4 inflow-phase features */
 #define FSI_GUESS_NIN 18
 
 /* A perceptron with nlayers dense layers: nin -> hidden -> ... -> hidden -> nout, tanh
@@ -56,13 +61,14 @@ fsi_status fsi_mlp_loss_grad(fsi_mlp *m, const float *X, const float *T, int64_t
 fsi_status fsi_mlp_train_step(fsi_mlp *m, const float *X, const float *T, int64_t n, float lr, float b1,
                               float b2, float eps, double *loss);
 
-/* (host) the 21 scales: s [7] of y1, s_d [7] of y1 - y2, s_o [7] of the output */
+/* (host) the 21 scales: s [7] of y1, floor [7] of sigma, gain [7] of the output correction
+ * (defaults 1, 0, 1) */
 fsi_status fsi_mlp_set_scales(fsi_mlp *m, const float *scales);
 /* X [V][FSI_GUESS_NIN] (device) from y1 = y_{n-1}, y2 = y_{n-2} (device [V][7]) and the
  * four inflow-phase features tfeat (host) */
 fsi_status fsi_guess_features(fsi_mlp *m, const double *y1, const double *y2, int64_t V, const float *tfeat,
                               float *X);
-/* training target T [V][7] = (y - (2 y1 - y2)) / s_o (device) */
+/* training target T [V][7] = (y - (2 y1 - y2)) / sigma (device), sigma from (y1, y2) */
 fsi_status fsi_guess_target(fsi_mlp *m, const double *y, const double *y1, const double *y2, int64_t V,
                             float *T);
 /* guess [V][7] (device): the extrapolation corrected by the network (tfeat and the work
@@ -72,10 +78,13 @@ fsi_status fsi_guess_predict(fsi_mlp *m, const double *y1, const double *y2, int
                              float *Xwork, double *guess);
 
 /* C [M][ldc] = alpha A B + beta C on the matrix cores (FP32); A(m,k) = A[m*sam + k*sak],
- * B(k,n) = B[k*sbk + n*sbn] (device) -- the dense layers' GEMM, exposed for testing */
+ * B(k,n) = B[k*sbk + n*sbn] (device) -- the dense layers' GEMM, exposed for testing.
+ * nsplit > 1 splits K over up to nsplit workgroups per 64x64 tile, with partial sums in
+ * work (device, nsplit * M * N floats, caller-owned), added in a fixed order.  K = 0 gives
+ * C = beta C, with A and B unused (may be NULL). */
 fsi_status fsi_gemm_f32(int32_t M, int32_t N, int32_t K, float alpha, const float *A, int64_t sam, int64_t sak,
-                        const float *B, int64_t sbk, int64_t sbn, float beta, float *C, int64_t ldc,
-                        void *hip_stream);
+                        const float *B, int64_t sbk, int64_t sbn, float beta, float *C, int64_t ldc, int32_t nsplit,
+                        float *work, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -9,8 +9,10 @@ Plain NumPy, one layer at a time, written from the definitions:
             dW_l = H_{l-1}^T dZ_l, db_l = column sums of dZ_l,
             dH_{l-1} = dZ_l W_l^T, dZ_{l-1} = dH_{l-1} (1 - H_{l-1}^2);
   Adam      Kingma and Ba (2015) with bias correction;
-  guess     g = 2 y1 - y2 + s_o * Y, features x = [y1 / s, (y1 - y2) / s_d, phase features],
-            target T = (y - (2 y1 - y2)) / s_o.
+  guess     g = 2 y1 - y2 + gain * sigma * Y, features x = [y1 / s, (y1 - y2) / sigma, phase
+            features], target T = (y - (2 y1 - y2)) / sigma, where per component c
+            sigma[c] = max(RMS over vertices of (y1 - y2)[:, c], floor[c]); the 21 scales
+            are s [7], floor [7], gain [7].
 The parameter vector stores W_1, b_1, W_2, b_2, ... with W_l [d_in][d_out] row-major.
 Pinned in tests/test_oracle_pins.py by central finite differences, the closed form of a
 single linear layer and the closed form of a first Adam step.
@@ -77,21 +79,26 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def step_sigma(y1, y2, scales):
+    d = np.asarray(y1, dtype=np.float64).reshape(-1, 7) - np.asarray(y2, dtype=np.float64).reshape(-1, 7)
+    floor = np.asarray(scales, dtype=np.float64)[7:14]
+    return np.maximum(np.sqrt(np.mean(d * d, axis=0)), floor)
+
+
 def features(y1, y2, scales, tfeat):
     y1 = np.asarray(y1, dtype=np.float64).reshape(-1, 7)
     y2 = np.asarray(y2, dtype=np.float64).reshape(-1, 7)
     s = np.asarray(scales, dtype=np.float64)
     X = np.empty((y1.shape[0], 18))
     X[:, 0:7] = y1 / s[0:7]
-    X[:, 7:14] = (y1 - y2) / s[7:14]
+    X[:, 7:14] = (y1 - y2) / step_sigma(y1, y2, scales)
     X[:, 14:18] = np.asarray(tfeat, dtype=np.float64)[None, :]
     return X
 
 
 def target(y, y1, y2, scales):
-    s = np.asarray(scales, dtype=np.float64)
     ext = 2.0 * np.asarray(y1).reshape(-1, 7) - np.asarray(y2).reshape(-1, 7)
-    return (np.asarray(y).reshape(-1, 7) - ext) / s[14:21]
+    return (np.asarray(y).reshape(-1, 7) - ext) / step_sigma(y1, y2, scales)
 
 
 def guess(y1, y2, out, scales):
@@ -99,4 +106,5 @@ def guess(y1, y2, out, scales):
     ext = 2.0 * np.asarray(y1).reshape(-1, 7) - np.asarray(y2).reshape(-1, 7)
     if out is None:
         return ext.ravel()
-    return (ext + s[14:21] * np.asarray(out, dtype=np.float64).reshape(-1, 7)).ravel()
+    corr = s[14:21] * step_sigma(y1, y2, scales) * np.asarray(out, dtype=np.float64).reshape(-1, 7)
+    return (ext + corr).ravel()

@@ -111,7 +111,7 @@ def load_library(path: str = LIB_PATH):
         "fsi_mlp_train_step": [vp, vp, vp, i64, flt, flt, flt, flt, vp], "fsi_mlp_set_scales": [vp, vp],
         "fsi_guess_features": [vp, vp, vp, i64, vp, vp], "fsi_guess_target": [vp, vp, vp, vp, i64, vp],
         "fsi_guess_predict": [vp, vp, vp, i64, vp, vp, vp],
-        "fsi_gemm_f32": [i32, i32, i32, flt, vp, i64, i64, vp, i64, i64, flt, vp, i64, vp],
+        "fsi_gemm_f32": [i32, i32, i32, flt, vp, i64, i64, vp, i64, i64, flt, vp, i64, i32, vp, vp],
     }
     for k, a in sig.items():
         f = getattr(L, k)
@@ -392,8 +392,9 @@ class MLP:
         return g
 
 
-def gemm_f32(A, B, C_=None, alpha=1.0, beta=0.0, transA=False, transB=False):
-    """C = alpha op(A) op(B) + beta C on the matrix cores (FP32 torch tensors on the GPU)."""
+def gemm_f32(A, B, C_=None, alpha=1.0, beta=0.0, transA=False, transB=False, nsplit=1):
+    """C = alpha op(A) op(B) + beta C on the matrix cores (FP32 torch tensors on the GPU);
+    nsplit > 1 splits K, with a workspace allocated here."""
     import torch
     M, K = (A.shape[1], A.shape[0]) if transA else A.shape
     K2, N = (B.shape[1], B.shape[0]) if transB else B.shape
@@ -402,8 +403,9 @@ def gemm_f32(A, B, C_=None, alpha=1.0, beta=0.0, transA=False, transB=False):
         C_ = torch.zeros((M, N), dtype=torch.float32, device=A.device)
     sam, sak = (1, A.shape[1]) if transA else (A.shape[1], 1)
     sbk, sbn = (1, B.shape[1]) if transB else (B.shape[1], 1)
+    work = torch.empty(nsplit * M * N, dtype=torch.float32, device=C_.device) if nsplit > 1 else None
     rc = load_library().fsi_gemm_f32(M, N, K, alpha, _fptr(A), sam, sak, _fptr(B), sbk, sbn, beta, _fptr(C_),
-                                      C_.shape[1], None)
+                                      C_.shape[1], nsplit, _fptr(work), None)
     if rc:
         raise FsiError(rc, "fsi_gemm_f32")
     return C_

@@ -3,15 +3,21 @@ against the plain guesses at an equal Newton target.
 
 The network (include/fsi_guess.h) corrects the linear extrapolation 2 y_{n-1} - y_{n-2};
 features, targets, forward and backward passes and Adam steps all run in the library's
-kernels.  Host NumPy only draws the initial weights and fits the 21 feature/output
-scales (root mean squares over the training snapshots, read back once).
+kernels.  Host NumPy only draws the initial weights and fits the 21 feature/output scales
+(root mean squares over the training snapshots, read back once); torch holds the pooled
+training rows and shuffles them into mini-batches.
 
-Evaluation at one step n (the same for every guess): Newton runs from the guess, with
-Dirichlet values imposed, until ||F|| <= 1e-6 ||F(y_{n-1})|| -- an absolute target fixed
-by the previous solution, so that a better guess is not held to a smaller relative base.
+The guess handed to Newton is whichever of the network's guess and the extrapolation has
+the smaller nonlinear residual (two residual evaluations): the residual test of §3 judges
+the network, and the extrapolation is the fallback.
 
-Run as a module for the comparison on the depth-1 tree:
-    python -m paper_1810_04289_amd.guess --train-steps 40 --eval-steps 12
+Evaluation at one step n, the same for every guess: Newton runs from the guess, with
+Dirichlet values imposed, until ||F|| <= 1e-6 ||F(y_{n-1})||.  The absolute target is fixed
+by the previous solution, so that a better guess is not held to a smaller relative base;
+for the previous-state guess it is exactly the plain solver's relative test.
+
+Run as a module for the comparison:
+    python -m paper_1810_04289_amd.guess --case tube
 """
 from __future__ import annotations
 
@@ -28,14 +34,26 @@ from . import workload as W
 
 PERIOD, U_MEAN, U_AMP = 0.8, 30.0, 15.0
 
+CASES = {
+    # straight compliant tube, ~2.1k vertices; ILU(3): with ILU(2) GMRES stagnates at the
+    # first compliant step after the rigid start
+    "tube": dict(mesh=lambda: W.tube_mesh(), opts=dict(nsub=4, overlap=1, ilu_level=3)),
+    # depth-1 tree, subdomains of the depth-3 benchmark's size
+    "tree1": dict(mesh=lambda: W.tree_mesh(depth=1, h=W.TREE_H[1]), opts=dict(nsub=33, overlap=1, ilu_level=3)),
+}
+
 
 def phase_features(t: float, dt: float, amp: float) -> np.ndarray:
     """Four features of the inflow at step time t: phase (sin, cos), peak velocity and its
-    rate of change, both relative to the mean inflow."""
+    change over the step, both relative to the mean inflow and the base amplitude."""
     w = 2.0 * math.pi / PERIOD
     U = W.inflow_peak(t, amp=amp)
-    dU = W.inflow_peak(t, amp=amp) - W.inflow_peak(t - dt, amp=amp)
+    dU = U - W.inflow_peak(t - dt, amp=amp)
     return np.array([math.sin(w * t), math.cos(w * t), U / U_MEAN, dU / (dt * w * U_AMP)], dtype=np.float32)
+
+
+def layer_dims(nin=fsi.GUESS_NIN, hidden=128, nlayers=4, nout=7):
+    return [(nin if l == 0 else hidden, nout if l == nlayers - 1 else hidden) for l in range(nlayers)]
 
 
 def init_params(dims, seed: int = 0, last_scale: float = 0.1) -> np.ndarray:
@@ -50,145 +68,278 @@ def init_params(dims, seed: int = 0, last_scale: float = 0.1) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def layer_dims(nin=fsi.GUESS_NIN, hidden=128, nlayers=4, nout=7):
-    return [(nin if l == 0 else hidden, nout if l == nlayers - 1 else hidden) for l in range(nlayers)]
-
-
 class LearnedGuess:
-    def __init__(self, V: int, hidden: int = 128, nlayers: int = 4, seed: int = 0):
-        self.V = V
+    """The network, its scales and its training on pooled snapshot rows."""
+
+    def __init__(self, V: int, hidden: int = 128, nlayers: int = 4, batch: int = 8192, seed: int = 0):
+        self.V, self.batch = V, batch
         self.dims = layer_dims(hidden=hidden, nlayers=nlayers)
-        self.net = fsi.MLP(fsi.GUESS_NIN, hidden, nlayers, 7, nmax=V)
+        self.net = fsi.MLP(fsi.GUESS_NIN, hidden, nlayers, 7, nmax=max(V, batch))
         self.net.set_params(init_params(self.dims, seed))
         self.scales = np.ones(21, dtype=np.float32)
 
-    def fit_scales(self, triples):
-        """triples: [(y_{n-2}, y_{n-1}, y_n)] device tensors [7V]."""
-        a = np.stack([t[1].cpu().numpy().reshape(-1, 7) for t in triples])
-        d = np.stack([(t[1] - t[2]).cpu().numpy().reshape(-1, 7) for t in triples])
-        r = np.stack([(t[2] - 2 * t[1] + t[0]).cpu().numpy().reshape(-1, 7) for t in triples])
-        rms = lambda x: np.sqrt(np.mean(x.reshape(-1, 7) ** 2, axis=0))
-        sc = np.concatenate([rms(a), rms(d), rms(r)])
-        sc = np.where(sc > 0, sc, 1.0)
+    def close(self):
+        self.net.close()
+
+    def fit_scales(self, samples):
+        """samples: [(y_{n-2}, y_{n-1}, y_n, tfeat)] with device state vectors [7V].  s is the
+        RMS of y_{n-1} over the snapshots, the sigma floor 1e-3 of the mean step change, and
+        the output gains start at 1."""
+        def rms(v):
+            return np.sqrt((v.reshape(-1, 7) ** 2).mean(0).cpu().numpy())
+        s = np.sqrt(np.mean([rms(y1) ** 2 for _, y1, _, _ in samples], axis=0))
+        sig = np.mean([rms(y1 - y2) for y2, y1, _, _ in samples], axis=0)
+        sc = np.concatenate([np.where(s > 0, s, 1.0), 1e-3 * sig + 1e-30, np.ones(7)])
         self.scales = sc.astype(np.float32)
         self.net.set_scales(self.scales)
 
-    def train(self, samples, steps: int = 300, lr: float = 1e-3, seed: int = 0, log=None):
-        """samples: [(y_{n-2}, y_{n-1}, y_n, tfeat)]; one Adam step per snapshot, snapshots in
-        a seeded random order per epoch.  Returns the loss history."""
-        data = []
+    GROUPS = {"u": (0, 1, 2), "p": (3,), "d": (4, 5, 6)}
+
+    def fit_gains(self, samples, groups=("u",)):
+        """Per component group (velocity u, pressure p, displacement d) the least-squares
+        weight of the network's correction on held-out snapshots, clipped to [0, 1]; groups
+        not listed get no correction.  By default only the velocity is corrected: pressure
+        and displacement, well predicted within the training period, carry that period's
+        start-up transient and come out worse than the extrapolation in the next one."""
+        import torch
+        num, den = np.zeros(7), np.zeros(7)
         for y2, y1, y, tf in samples:
-            # features from (y1, y2) and the target; kept on the device for the epochs
-            data.append((self.net.features(y1, y2, tf), self.net.target(y, y1, y2)))
-        rng = np.random.default_rng(seed)
-        hist, k = [], 0
+            T = self.net.target(y, y1, y2)
+            out = self.net.forward(self.net.features(y1, y2, tf))
+            num += (T * out).sum(0).double().cpu().numpy()
+            den += (out * out).sum(0).double().cpu().numpy()
+        gain = np.zeros(7)
+        for name in groups:
+            g = list(self.GROUPS[name])
+            gain[g] = np.clip(num[g].sum() / max(den[g].sum(), 1e-300), 0.0, 1.0)
+        self.scales[14:21] = gain
+        self.net.set_scales(self.scales)
+        return gain
+
+    def train(self, samples, steps: int = 2000, lr: float = 2e-3, lr_end: float = 1e-4, seed: int = 0, log=None):
+        """Adam on mini-batches of rows drawn without replacement from all snapshots (a new
+        permutation per epoch), learning rate on a cosine from lr to lr_end.  Returns the
+        loss history."""
+        import torch
+        X = torch.cat([self.net.features(y1, y2, tf) for y2, y1, _, tf in samples])
+        T = torch.cat([self.net.target(y, y1, y2) for y2, y1, y, _ in samples])
+        N = X.shape[0]
+        B = min(self.batch, N)
+        gen = torch.Generator(device=X.device)
+        gen.manual_seed(seed)
+        hist, k, epoch = [], 0, 0
         while k < steps:
-            for i in rng.permutation(len(data)):
+            perm = torch.randperm(N, generator=gen, device=X.device)
+            Xp, Tp = X[perm].contiguous(), T[perm].contiguous()
+            for b0 in range(0, N - B + 1, B):
+                lr_k = lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * k / steps))
+                hist.append(self.net.train_step(Xp[b0:b0 + B], Tp[b0:b0 + B], lr=lr_k))
+                k += 1
                 if k >= steps:
                     break
-                hist.append(self.net.train_step(data[i][0], data[i][1], lr=lr))
-                k += 1
-            if log:
-                log(f"[guess] train step {k}: loss {np.mean(hist[-len(data):]):.4e}")
+            epoch += 1
+            if log and (epoch % 10 == 0 or k >= steps):
+                log(f"[guess] epoch {epoch} step {k}: loss {np.mean(hist[-(N // B):]):.4e}")
         return hist
 
     def predict(self, y1, y2, tfeat=None):
         return self.net.predict(y1, y2, tfeat)
 
 
-def _norm(s, y, F):
-    s.residual(y, F, check=False)
-    return float(F.norm())
+class Stepper:
+    """The plain solver on one case: backward Euler steps with the pulsatile inflow, the
+    wall held rigid for the first two steps of a run from rest."""
+
+    def __init__(self, case: str, dt: float):
+        c = CASES[case]
+        self.mesh = c["mesh"]()
+        opts = dict(c["opts"], gmres_maxit=600, newton_maxit=30)
+        self.s = fsi.Solver(self.mesh, W.physics_config1(), opts)
+        self.dt = dt
+        self.rigid = W.rigid_wall_mask(self.mesh)
+        self.F = self.s.vec()
+
+    def close(self):
+        self.s.close()
+
+    def set_step(self, k: int, amp: float, y_prev):
+        import torch
+        t = (k + 1) * self.dt
+        g = torch.as_tensor(W.dirichlet_values(self.mesh, W.inflow_peak(t, amp=amp))).to(self.s.device)
+        self.s.set_step(t, self.dt, y_prev, g, None, self.rigid if k < 2 else None)
+        return t
+
+    def fnorm(self, y):
+        """||F(y)|| with the step's Dirichlet values imposed on a copy of y (infinite where
+        the residual is undefined, e.g. an inverted element)."""
+        tmp = y.clone()
+        self.s.impose_dirichlet(tmp)
+        if self.s.residual(tmp, self.F, check=False):
+            return math.inf
+        return float(self.F.norm())
+
+    def solve(self, y, rtol=1e-6, atol=0.0):
+        self.s.set_newton_tol(rtol, atol)
+        st, rc = self.s.newton_solve(y, check=False)
+        return st, rc
 
 
-def run(depth=1, train_steps=40, eval_steps=12, amp_eval=18.0, nsub=None, ilu=3, train_iters=400, seed=0,
-        log=print):
+def run(case="tube", dt=2e-3, train_steps=400, eval_steps=60, amp_eval=18.0, train_iters=2000, batch=8192, seed=0,
+        skip=0, eval_offset=0, groups=("u",), log=print):
+    """Trains on one inflow period of the plain solver's steps (amplitude 15 cm/s; the first
+    `skip` steps of the start from rest left out), continues with amplitude amp_eval, and
+    compares the guesses over eval_steps steps from eval_offset steps into the next period."""
     import torch
-    dt = 1e-3
-    mesh = W.tree_mesh(depth=depth, h=W.TREE_H[depth])
-    if nsub is None:
-        nsub = max(1, round(256 * mesh.nverts / 202715))
-    ph = W.physics_config1()
-    s = fsi.Solver(mesh, ph, dict(nsub=nsub, overlap=1, ilu_level=ilu, gmres_maxit=600, newton_maxit=30))
-    dev = s.device
-    rigid = W.rigid_wall_mask(mesh)
+    S = Stepper(case, dt)
+    V = S.mesh.nverts
 
-    def trajectory(amp, nsteps, on_step=None):
-        ys = [torch.zeros(s.n, dtype=torch.float64, device=dev)]
-        for k in range(nsteps):
-            t = (k + 1) * dt
-            g = torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak(t, amp=amp))).to(dev)
-            s.set_step(t, dt, ys[-1], g, None, rigid if k < 2 else None)
-            if on_step is not None and k >= 4:
-                on_step(k, t, ys, amp)
-            s.set_newton_tol(1e-6, 0.0)
-            y = ys[-1].clone()
-            st, rc = s.newton_solve(y, check=False)
-            if rc:
-                raise RuntimeError(f"plain step {k} failed: {rc}")
-            ys.append(y)
-        return ys
-
-    # training data: the plain solver's own steps (compliant steps from k = 4 on)
+    # the plain solver's trajectory; training uses steps 4 .. train_steps (wall compliant
+    # for both previous states)
     t0 = time.perf_counter()
-    ys = trajectory(U_AMP, train_steps + 4)
-    samples = [(ys[k - 1], ys[k], ys[k + 1], phase_features((k + 1) * dt, dt, U_AMP)) for k in range(4, len(ys) - 1)]
-    lg = LearnedGuess(mesh.nverts, seed=seed)
-    lg.fit_scales([(a, b, c) for a, b, c, _ in samples])
+    ys = [S.s.vec()]
+    for k in range(train_steps):
+        S.set_step(k, U_AMP, ys[-1])
+        y = ys[-1].clone()
+        st, rc = S.solve(y)
+        if rc:
+            raise RuntimeError(f"plain step {k} failed: {rc}")
+        ys.append(y)
+        if log and (k + 1) % 50 == 0:
+            log(f"[guess] plain step {k + 1}: NI {st['newton_iters']} LI {st['linear_iters']}")
+    samples = [(ys[k - 1], ys[k], ys[k + 1], phase_features((k + 1) * dt, dt, U_AMP))
+               for k in range(max(4, skip), train_steps)]
     t_data = time.perf_counter() - t0
+
+    lg = LearnedGuess(V, batch=batch, seed=seed)
+    lg.fit_scales(samples)
+    # every tenth snapshot is held out for the gains
+    fit = [x for i, x in enumerate(samples) if i % 10 != 5]
+    held = [x for i, x in enumerate(samples) if i % 10 == 5]
     t0 = time.perf_counter()
-    hist = lg.train(samples, steps=train_iters, seed=seed, log=log)
+    hist = lg.train(fit, steps=train_iters, seed=seed, log=log)
+    gain = lg.fit_gains(held, groups)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    if log:
+        log(f"[guess] output gains (u, p, d): {gain[0]:.3f} {gain[3]:.3f} {gain[4]:.3f}")
 
-    # evaluation on a perturbed inflow: each guess solved to the same absolute target
-    F = torch.empty(s.n, dtype=torch.float64, device=dev)
-    rec = {"previous": [], "extrapolation": [], "learned": []}
-    f0s = {"previous": [], "extrapolation": [], "learned": []}
-
-    def compare(k, t, ys_, amp):
-        y1, y2 = ys_[-1], ys_[-2]
-        tmp = y1.clone()
-        s.impose_dirichlet(tmp)
-        target = 1e-6 * _norm(s, tmp, F)
-        guesses = {"previous": y1.clone(), "extrapolation": lg.predict(y1, y2),
-                   "learned": lg.predict(y1, y2, phase_features(t, dt, amp))}
-        for name, g in guesses.items():
-            tmp.copy_(g)
-            s.impose_dirichlet(tmp)
-            f0s[name].append(_norm(s, tmp, F))
-            s.set_newton_tol(0.0, target)
+    names = ("previous", "extrapolation", "learned")
+    rec = {n: [] for n in names}
+    net_f0, picked, l2 = [], 0, {"extrapolation": [], "network": []}
+    y1, y2 = ys[-1], ys[-2]
+    nfit = len(fit)
+    del ys, samples, fit, held
+    for j in range(eval_offset):  # plain steps into the next period
+        S.set_step(train_steps + j, amp_eval, y1)
+        y = y1.clone()
+        st, rc = S.solve(y)
+        if rc:
+            raise RuntimeError(f"plain step {train_steps + j} failed: {rc}")
+        y2, y1 = y1, y
+    for j in range(eval_steps):
+        k = train_steps + eval_offset + j
+        t = S.set_step(k, amp_eval, y1)
+        target = 1e-6 * S.fnorm(y1)
+        f_prev = S.fnorm(y1)
+        out = {}
+        for name in names:
             torch.cuda.synchronize()
             tt = time.perf_counter()
-            st, rc = s.newton_solve(g, check=False)
+            if name == "previous":
+                g = y1.clone()
+            elif name == "extrapolation":
+                g = lg.predict(y1, y2)
+            else:
+                ge = lg.predict(y1, y2)
+                gn = lg.predict(y1, y2, phase_features(t, dt, amp_eval))
+                fe, fn = S.fnorm(ge), S.fnorm(gn)
+                net_f0.append(fn / f_prev)
+                g = gn.clone() if fn < fe else ge.clone()
+                picked += fn < fe
+            f0 = S.fnorm(g)
+            st, rc = S.solve(g, rtol=0.0, atol=target)
             torch.cuda.synchronize()
-            rec[name].append(dict(rc=rc, NI=st["newton_iters"], LI=st["linear_iters"], sec=time.perf_counter() - tt))
+            rec[name].append(dict(rc=rc, NI=st["newton_iters"], LI=st["linear_iters"], F0=f0 / f_prev,
+                                  fnorm=st["fnorm"] / target, sec=time.perf_counter() - tt))
+            out[name] = g
+        # errors of the two predictions against the solution, relative to the step's change,
+        # per component group (velocity, pressure, displacement)
+        dy = (out["previous"] - y1).view(-1, 7)
+        for nm, gg in (("extrapolation", ge), ("network", gn)):
+            e = (gg - out["previous"]).view(-1, 7)
+            l2[nm].append([float(e[:, a:b].norm() / max(float(dy[:, a:b].norm()), 1e-300))
+                           for a, b in ((0, 3), (3, 4), (4, 7))])
+        # the trajectory continues from the plain solver's solution
+        y2, y1 = y1, out["previous"]
+        if log and (j + 1) % 10 == 0:
+            log(f"[guess] eval step {j + 1}: " + ", ".join(f"{n} NI {rec[n][-1]['NI']}" for n in names))
 
-    trajectory(amp_eval, eval_steps + 4, on_step=compare)
-    summary = {"depth": depth, "vertices": mesh.nverts, "unknowns": s.n, "nsub": nsub, "ilu": ilu,
-               "train_snapshots": len(samples), "train_adam_steps": train_iters, "eval_steps": len(rec["learned"]),
-               "amp_train": U_AMP, "amp_eval": amp_eval, "data_s": round(t_data, 2), "train_s": round(t_train, 2),
-               "loss_first": hist[0], "loss_last": float(np.mean(hist[-len(samples):]))}
+    summary = {"case": case, "groups": "".join(groups), "vertices": V, "unknowns": S.s.n, "dt": dt, "train_snapshots": nfit,
+               "train_rows": nfit * V, "skip": skip, "adam_steps": train_iters, "batch": batch,
+               "eval_steps": eval_steps, "amp_train": U_AMP, "amp_eval": amp_eval, "data_s": round(t_data, 2),
+               "train_s": round(t_train, 2), "loss_first": float(np.mean(hist[:10])),
+               "loss_last": float(np.mean(hist[-10:])), "gains_upd": [float(gain[0]), float(gain[3]), float(gain[4])],
+               "network_F0_rel": float(np.mean(net_f0)), "eval_offset": eval_offset,
+               "rel_err_upd": {nm: np.mean(v, axis=0).tolist() for nm, v in l2.items()},
+               "network_picked": picked}
     for name, r in rec.items():
-        summary[name] = {"failures": sum(1 for x in r if x["rc"]), "NI": float(np.mean([x["NI"] for x in r])),
+        summary[name] = {"failures": sum(1 for x in r if x["rc"]),
+                         "max_fnorm_over_target": float(max(x["fnorm"] for x in r)),
+                         "NI": float(np.mean([x["NI"] for x in r])),
                          "LI_per_step": float(np.mean([x["LI"] for x in r])),
                          "s_per_step": float(np.mean([x["sec"] for x in r])),
-                         "F0_rel": float(np.mean(np.array(f0s[name]) / np.array(f0s["previous"])))}
-    s.close()
-    lg.net.close()
+                         "F0_rel": float(np.mean([x["F0"] for x in r]))}
+    S.close()
+    lg.close()
     return summary
+
+
+def train_bench(batch=8192, steps=200, warmup=20, hidden=128, nlayers=4, seed=0):
+    """Adam steps of the guess network on one seeded synthetic batch (FP32 rows of unit
+    variance): time per step and the dense-layer FLOP rate it implies."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dims = layer_dims(hidden=hidden, nlayers=nlayers)
+    net = fsi.MLP(fsi.GUESS_NIN, hidden, nlayers, 7, nmax=batch)
+    net.set_params(init_params(dims, seed))
+    X = torch.as_tensor(rng.standard_normal((batch, fsi.GUESS_NIN)).astype(np.float32)).cuda()
+    T = torch.as_tensor(rng.standard_normal((batch, 7)).astype(np.float32)).cuda()
+    for _ in range(warmup):
+        net.train_step(X, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = net.train_step(X, T)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    # forward, weight gradients and input gradients (all layers but the first)
+    mac = sum(a * b for a, b in dims)
+    flops = 2.0 * batch * (2 * mac + sum(a * b for a, b in dims[1:]))
+    net.close()
+    return {"batch": batch, "dims": dims, "steps": steps, "ms_per_step": sec * 1e3, "gflop_per_step": flops / 1e9,
+            "tflops": flops / sec / 1e12, "loss": loss}
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--depth", type=int, default=1)
-    ap.add_argument("--train-steps", type=int, default=40)
-    ap.add_argument("--eval-steps", type=int, default=12)
+    ap.add_argument("--case", default="tube", choices=sorted(CASES))
+    ap.add_argument("--dt", type=float, default=2e-3)
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--eval-steps", type=int, default=60)
     ap.add_argument("--amp-eval", type=float, default=18.0)
-    ap.add_argument("--train-iters", type=int, default=400)
+    ap.add_argument("--train-iters", type=int, default=2000)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--skip", type=int, default=0, help="start-up steps left out of training")
+    ap.add_argument("--eval-offset", type=int, default=0, help="plain steps into the next period before comparing")
+    ap.add_argument("--groups", default="u", help="component groups the network corrects, e.g. u or upd")
+    ap.add_argument("--train-bench", action="store_true", help="time Adam steps on a synthetic batch only")
     a = ap.parse_args()
-    out = run(depth=a.depth, train_steps=a.train_steps, eval_steps=a.eval_steps, amp_eval=a.amp_eval,
-              train_iters=a.train_iters, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    if a.train_bench:
+        print(json.dumps(train_bench(batch=a.batch)), flush=True)
+        return
+    out = run(case=a.case, dt=a.dt, train_steps=a.train_steps, eval_steps=a.eval_steps, amp_eval=a.amp_eval,
+              train_iters=a.train_iters, batch=a.batch, skip=a.skip, eval_offset=a.eval_offset, groups=tuple(a.groups),
+              log=lambda *x: print(*x, file=sys.stderr, flush=True))
     print(json.dumps(out), flush=True)
 
 

@@ -574,13 +574,32 @@ def test_adam_first_step_closed_form():
 
 
 def test_guess_target_round_trip():
-    # guess(y1, y2, target(y, y1, y2)) = y: the network output is a scaled correction of the
-    # linear extrapolation
+    # guess(y1, y2, target(y, y1, y2)) = y with unit gains: the network output is the
+    # correction of the linear extrapolation in units of the last step's change
     from oracle import mlp
     rng = np.random.default_rng(14)
     y, y1, y2 = (rng.standard_normal(7 * 9) for _ in range(3))
-    s = rng.uniform(0.5, 2.0, 21)
+    s = np.concatenate([rng.uniform(0.5, 2.0, 7), np.zeros(7), np.ones(7)])
     T = mlp.target(y, y1, y2, s)
     assert np.allclose(mlp.guess(y1, y2, T, s), y, rtol=1e-13, atol=1e-13)
     X = mlp.features(y1, y2, s, [0.1, 0.2, 0.3, 0.4])
     assert np.allclose(X[:, 0:7] * s[0:7], y1.reshape(-1, 7)) and np.allclose(X[:, 14:18], [0.1, 0.2, 0.3, 0.4])
+    # the change features have unit root mean square per component
+    assert np.allclose(np.sqrt(np.mean(X[:, 7:14] ** 2, axis=0)), 1.0, rtol=1e-13)
+    # a zero gain switches a component's correction off
+    s0 = s.copy()
+    s0[14 + 3] = 0.0
+    g = mlp.guess(y1, y2, T, s0).reshape(-1, 7)
+    assert np.allclose(g[:, 3], (2 * y1 - y2).reshape(-1, 7)[:, 3], rtol=1e-14, atol=1e-14)
+
+
+def test_guess_step_scale():
+    # sigma: a uniform change c per component gives |c|; a floor above the RMS replaces it
+    from oracle import mlp
+    c = np.array([1.0, -2.0, 0.5, 3.0, -1e-3, 0.0, 7.0])
+    y2 = np.random.default_rng(15).standard_normal((11, 7))
+    y1 = y2 + c
+    s = np.concatenate([np.ones(7), np.zeros(7), np.ones(7)])
+    assert np.allclose(mlp.step_sigma(y1, y2, s), np.abs(c), rtol=1e-13, atol=1e-15)
+    s[7:14] = 2.0
+    assert np.allclose(mlp.step_sigma(y1, y2, s), np.maximum(np.abs(c), 2.0), rtol=1e-13)
