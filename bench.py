@@ -71,9 +71,10 @@ def sweep_bytes(s, precision: int = 0) -> dict:
     return dict(ilu_fwd=fwd, ilu_bwd=bwd, local_blocks=NB, local_rows=R, l_blocks=nL, u_blocks=nU)
 
 
-def stored_traffic(kernel: str, precision: int):
+def stored_traffic(kernel: str, precision: int, config: dict):
     """HBM bytes per launch measured with rocprofv3 counters, if the profile on record was
-    taken with the current sweep source and the same sweep precision; None otherwise."""
+    taken with the current sweep source, the same sweep precision and the same Schwarz
+    configuration (subdomains, fill level, overlap, ordering); None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3.json")
     try:
@@ -83,8 +84,14 @@ def stored_traffic(kernel: str, precision: int):
     src = open(os.path.join(ROOT, "paper_1810_04289_amd", "csrc", "ilu.hip"), "rb").read()
     if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest() or rec.get("precision", 0) != precision:
         return None
+    rec_cfg = rec.get("config", {"nsub": 256, "ilu_level": 3, "overlap": 1, "ordering": 0})
+    if any(rec_cfg.get(k) != config.get(k) for k in ("nsub", "ilu_level", "overlap", "ordering")):
+        return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+ORDERING = {0: "RCM", 1: "1WD"}
 
 
 def spmv_bytes(s) -> int:
@@ -92,7 +99,8 @@ def spmv_bytes(s) -> int:
     return s.nnzb * (49 * 8 + 4) + 4 * (s.V + 1) + 2 * 7 * s.V * 8
 
 
-def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1) -> dict:
+def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1,
+                 ordering: int = 0) -> dict:
     """The oracle (1 host core) timed on a bounded sample and scaled to the workload.
 
     Sample: the depth-1 tree (about 26k vertices, cut into subdomains of the workload's
@@ -105,7 +113,8 @@ def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, over
     m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     ph = W.physics_config1()
     ns = max(1, round(nsub_work * m.nverts / V_work))
-    o = O.Oracle(m, ph, dict(nsub=ns, overlap=overlap, ilu_level=ilu_level, gmres_rtol=0.0, gmres_maxit=8))
+    o = O.Oracle(m, ph, dict(nsub=ns, overlap=overlap, ilu_level=ilu_level, ordering=ordering, gmres_rtol=0.0,
+                             gmres_maxit=8))
     g = W.dirichlet_values(m, 30.0)
     y0 = W.perturbed_state(m, np.zeros(m.n), seed=1)
     o.set_step(1e-3, 1e-3, np.zeros(m.n), g)
@@ -126,7 +135,8 @@ def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, over
                 counts["gmres_iters"] * t_it)
     scale = V_work / m.nverts
     return {"value": per_step * scale, "unit": "s/step", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle phases on the depth-1 tree ({m.nverts} vertices, {ns} subdomains, ILU({ilu_level})): "
+            "sample": (f"oracle phases on the depth-1 tree ({m.nverts} vertices, {ns} subdomains, ILU({ilu_level}), "
+                       f"{ORDERING[ordering]} ordering): "
                        f"FuncEval {t_fe:.3f}s, JacEval {t_je:.3f}s, PCSetUp {t_ps:.3f}s, GMRES iter {t_it:.4f}s; "
                        f"combined with the GPU run's per-step counts {counts} and scaled by {scale:.2f} "
                        f"(vertex ratio)"),
@@ -153,6 +163,7 @@ def main():
     ap.add_argument("--ilu", type=int, default=3)
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--overlap", type=int, default=1)
+    ap.add_argument("--ordering", type=int, default=0, help="subdomain ordering: 0 RCM, 1 one-way dissection")
     ap.add_argument("--jac-lag", type=int, default=1, help="Newton iterations per Jacobian and Schwarz setup")
     ap.add_argument("--precision", type=int, default=0,
                     help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
@@ -175,7 +186,8 @@ def main():
     t0 = time.perf_counter()
     mesh = W.tree_mesh(depth=args.depth, h=W.TREE_H[args.depth])
     ph = W.physics_config1()
-    opts = dict(nsub=args.nsub, overlap=args.overlap, ilu_level=args.ilu, jac_lag=args.jac_lag, gmres_restart=30,
+    opts = dict(nsub=args.nsub, overlap=args.overlap, ilu_level=args.ilu, ordering=args.ordering, jac_lag=args.jac_lag,
+                gmres_restart=30,
                 gmres_maxit=600,
                 gmres_rtol=1e-3, newton_rtol=1e-6, newton_maxit=20, precision=args.precision)
     s = fsi.Solver(mesh, ph, opts)
@@ -250,6 +262,7 @@ def main():
     }
     phases = {k: float(np.mean([x[k] for x in stats])) for k in
               ("t_funceval", "t_jaceval", "t_pcsetup", "t_pcapply", "t_kspsolve")}
+    schwarz_cfg = dict(nsub=args.nsub, ilu_level=args.ilu, overlap=args.overlap, ordering=args.ordering)
     out = {
         "metric": METRIC, "value": round(sec_per_step, 5), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * sec_per_step, 2), "higher_is_better": False,
@@ -258,25 +271,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bifurcating compliant tree depth {args.depth}, {mesh.nverts} vertices, "
                                f"{mesh.ntets} tets, {s.n} unknowns, dt {dt}, {args.nsub} RAS subdomains overlap {args.overlap}, "
-                               f"ILU({args.ilu}), GMRES(30) rtol 1e-3, Newton rtol 1e-6"
+                               f"ILU({args.ilu}), {ORDERING[args.ordering]} ordering, GMRES(30) rtol 1e-3, Newton rtol 1e-6"
                                + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps"}[args.precision],
                    "nverts": mesh.nverts, "ntets": mesh.ntets, "n": s.n, "nnzb": s.nnzb, "nsub": args.nsub,
-                   "ilu_level": args.ilu, "overlap": args.overlap, "jac_lag": args.jac_lag, "dt": dt, "local_blocks": sw["local_blocks"],
+                   "ilu_level": args.ilu, "overlap": args.overlap, "ordering": args.ordering, "jac_lag": args.jac_lag,
+                   "dt": dt, "local_blocks": sw["local_blocks"],
                    "local_rows": sw["local_rows"]},
         "NI": NI, "LI": round(LI, 2), "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK, 4) if achieved else None,
-                     "traffic": stored_traffic(dom, args.precision), "bytes_per_launch": sw[dom], "avg_us": t_dom,
+                     "traffic": stored_traffic(dom, args.precision, schwarz_cfg), "bytes_per_launch": sw[dom], "avg_us": t_dom,
                      "other_sweep": {"kernel": other, "bytes_per_launch": sw[other], "avg_us": t_other,
                                      "achieved": round(sw[other] / (t_other * 1e-6) / 1e9, 1) if t_other else None,
-                                     "traffic": stored_traffic(other, args.precision)}},
+                                     "traffic": stored_traffic(other, args.precision, schwarz_cfg)}},
         "spmv": {"achieved_GBs": round(spmv_gbs, 1) if spmv_gbs else None, "bytes": sb,
                  "frac": round(spmv_gbs / HBM_PEAK, 4) if spmv_gbs else None},
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap)
+        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap, args.ordering)
     print(json.dumps(out), flush=True)
     s.close()
 

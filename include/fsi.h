@@ -66,13 +66,21 @@ typedef struct {
  * the stabilization parameter. */
 typedef struct { double rho_f, mu_f, rho_s, E_s, nu_s, eta_s, C_I; } fsi_physics;
 
+/* Subdomain orderings (§4.5, Table 4).  RCM: reverse Cuthill-McKee of the subdomain's
+ * vertex graph from a George-Liu pseudo-peripheral vertex.  1WD: one-way dissection -- the
+ * BFS levels from that vertex, every (ilu_level + 3)-th level a separator; the connected
+ * blocks between separators first, each in RCM order, then the separator levels, each in
+ * RCM order.  With ILU(l) no fill joins two separators, and rows of different blocks are
+ * independent in the triangular sweeps. */
+enum { FSI_ORDER_RCM = 0, FSI_ORDER_1WD = 1 };
+
 /* Solver options (§3, §4).  Defaults of the paper: overlap 1, Newton rtol 1e-6, GMRES
  * rtol 1e-3, Jacobian lag 1, subdomain ILU(1), RCM subdomain ordering. */
 typedef struct {
   int32_t nsub;             /* number of Schwarz subdomains (>= 1) */
   int32_t overlap;          /* delta: layers of vertex-graph neighbours added (>= 0) */
   int32_t ilu_level;        /* l of ILU(l), 0..8 */
-  int32_t ordering;         /* 0 = reverse Cuthill-McKee (the only ordering) */
+  int32_t ordering;         /* FSI_ORDER_RCM or FSI_ORDER_1WD (§4.5, Table 4) */
   const int32_t *part;      /* (host) [nverts] subdomain of each vertex, or NULL for
                                recursive coordinate bisection */
   int32_t gmres_restart;    /* 1..200 */

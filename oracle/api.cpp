@@ -15,6 +15,7 @@ int fsio_create(const fsio_mesh* m, const fsio_physics* ph, const fsio_opts* o, 
     return FSIO_ERR_ARG;
   if (o->nsub <= 0 || o->overlap < 0 || o->gmres_restart <= 0 || o->gmres_restart > 200) return FSIO_ERR_ARG;
   if (o->ilu_level < 0 || o->ilu_level > 8) return FSIO_ERR_ARG;
+  if (o->ordering != 0 && o->ordering != 1) return FSIO_ERR_ARG;  // RCM, 1WD
   fsio_solver* s = new (std::nothrow) fsio_solver();
   if (!s) return FSIO_ERR_OOM;
   s->V = m->nverts;

@@ -150,8 +150,77 @@ static std::vector<int> rcm_order(const fsio_solver& s, const std::vector<int>& 
   return order;
 }
 
+// ---------------------------------------------------------------------------------------
+// One-way dissection (§4.5, Table 4) on the vertex graph induced by a vertex set.  Each
+// connected piece, taken in the order RCM takes them, gets the level structure rooted at
+// RCM's pseudo-peripheral vertex, L_0 .. L_{h-1}.  Levels L_j with (j + 1) % sep == 0 and
+// j < h - 1 are separators.  The remaining vertices split into connected blocks; blocks
+// come first, in order of their smallest (degree, id) vertex, each ordered by RCM on its
+// own vertices; the separator levels follow in ascending j, each ordered by RCM on its
+// vertices.  Blocks do not touch each other, so their rows are independent.
+// ---------------------------------------------------------------------------------------
+static std::vector<int> onewd_order(const fsio_solver& s, const std::vector<int>& set, int sep) {
+  Induced G;
+  G.s = &s;
+  G.loc.assign(s.V, -1);
+  for (size_t i = 0; i < set.size(); ++i) G.loc[set[i]] = (int)i;
+  G.deg.assign(s.V, 0);
+  for (int v : set)
+    for (int k = s.J.rowptr[v]; k < s.J.rowptr[v + 1]; ++k) {
+      int y = s.J.colind[k];
+      if (y != v && G.in(y)) G.deg[v]++;
+    }
+  std::vector<char> vis(s.V, 0);
+  std::vector<int> order;
+  while (order.size() < set.size()) {
+    int start = -1;
+    for (int v : set)
+      if (!vis[v] && (start < 0 || less_dg(G, v, start))) start = v;
+    int r = pseudo_peripheral(G, start);
+    std::vector<std::vector<int>> L;
+    bfs_levels(G, r, L);
+    const int h = (int)L.size();
+    std::vector<char> is_sep(s.V, 0);
+    std::vector<int> comp;
+    for (int j = 0; j < h; ++j)
+      for (int v : L[j]) {
+        vis[v] = 1;
+        comp.push_back(v);
+        if ((j + 1) % sep == 0 && j < h - 1) is_sep[v] = 1;
+      }
+    // blocks: connected pieces of the non-separator vertices, by smallest (degree, id)
+    std::vector<int> cand;
+    for (int v : comp)
+      if (!is_sep[v]) cand.push_back(v);
+    std::sort(cand.begin(), cand.end(), [&](int a, int b) { return less_dg(G, a, b); });
+    std::vector<char> taken(s.V, 0);
+    for (int v0 : cand) {
+      if (taken[v0]) continue;
+      std::vector<int> blk = {v0};
+      taken[v0] = 1;
+      for (size_t q = 0; q < blk.size(); ++q) {
+        int x = blk[q];
+        for (int k = s.J.rowptr[x]; k < s.J.rowptr[x + 1]; ++k) {
+          int y = s.J.colind[k];
+          if (y != x && G.in(y) && !is_sep[y] && !taken[y]) { taken[y] = 1; blk.push_back(y); }
+        }
+      }
+      std::sort(blk.begin(), blk.end());
+      std::vector<int> o = rcm_order(s, blk);
+      order.insert(order.end(), o.begin(), o.end());
+    }
+    for (int j = sep - 1; j < h - 1; j += sep) {
+      std::vector<int> lv(L[j]);
+      std::sort(lv.begin(), lv.end());
+      std::vector<int> o = rcm_order(s, lv);
+      order.insert(order.end(), o.begin(), o.end());
+    }
+  }
+  return order;
+}
+
 // Extended submeshes (§3): owned vertices plus delta rings of vertex-graph neighbours,
-// reordered by RCM, with the sub-block pattern of R J R^T and its source blocks.
+// reordered by RCM or 1WD, with the sub-block pattern of R J R^T and its source blocks.
 int build_subdomains(fsio_solver& s) {
   const int ns = s.opts.nsub;
   s.subs.assign(ns, Sub());
@@ -171,7 +240,13 @@ int build_subdomains(fsio_solver& s) {
       frontier.swap(nxt);
     }
     std::sort(set.begin(), set.end());
-    S.verts = rcm_order(s, set);
+    if (s.opts.ordering == 1) {
+      // separators every ilu_level + 3 levels: a fill path between two separators crosses
+      // ilu_level + 2 block levels and so exceeds the kept fill level
+      S.verts = onewd_order(s, set, s.opts.ilu_level + 3);
+    } else {
+      S.verts = rcm_order(s, set);
+    }
     const int m = (int)S.verts.size();
     std::vector<int> loc(s.V, -1);
     for (int l = 0; l < m; ++l) loc[S.verts[l]] = l;

@@ -524,7 +524,7 @@ fsi_status fsi_create(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* 
       (m->nbfaces > 0 && (!m->bfaces || !m->bface_tag)) || m->nbfaces < 0)
     return FSI_ERR_ARG;
   if (o->nsub <= 0 || o->nsub > m->nverts || o->overlap < 0 || o->ilu_level < 0 || o->ilu_level > 8 ||
-      o->gmres_restart <= 0 || o->gmres_restart > kMaxRestart || o->gmres_maxit <= 0 || o->ordering != 0 ||
+      o->gmres_restart <= 0 || o->gmres_restart > kMaxRestart || o->gmres_maxit <= 0 || (o->ordering != FSI_ORDER_RCM && o->ordering != FSI_ORDER_1WD) ||
       o->precision < FSI_PREC_FP64 || o->precision > FSI_PREC_BF16 || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
     return FSI_ERR_ARG;
   fsi_solver* s = new (std::nothrow) fsi_solver();

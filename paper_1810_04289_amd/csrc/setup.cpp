@@ -262,6 +262,91 @@ static void rcm(const HostSetup& h, const std::vector<int32_t>& set, std::vector
   out.assign(seq.rbegin(), seq.rend());
 }
 
+// ---------------------------------------------------------------------------------------
+// One-way dissection (§4.5, Table 4).  Connected pieces are found as in rcm() (smallest
+// unfinished vertex by (degree, id), moved to the same pseudo-peripheral vertex).  The
+// piece's BFS levels from that vertex are 0 .. h-1; level j is a separator when
+// (j + 1) % sep == 0 and j < h - 1.  The other vertices of the piece fall into connected
+// blocks, taken in ascending (degree, id) of their first vertex; each block is ordered by
+// rcm() on its own vertices, then each separator level, in ascending j, by rcm() on its
+// vertices.  Rows of different blocks never meet, so the triangular sweeps run them side
+// by side; the separators come last, after every block they border.
+// ---------------------------------------------------------------------------------------
+static void onewd(const HostSetup& h, const std::vector<int32_t>& set, int sep, std::vector<int32_t>& out) {
+  SubGraph G;
+  G.h = &h;
+  G.deg.assign(h.V, -1);
+  for (int v : set) G.deg[v] = 0;
+  for (int v : set)
+    for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+      int u = h.colind[k];
+      if (u != v && G.has(u)) G.deg[v]++;
+    }
+  std::vector<int32_t> stamp(h.V, -1), level(h.V, -1), blockof(h.V, -1);
+  std::vector<uint8_t> done(h.V, 0);
+  int tag = 0;
+  std::vector<int32_t> sorted_set(set);
+  std::sort(sorted_set.begin(), sorted_set.end(), [&](int a, int b) { return G.before(a, b); });
+  out.clear();
+  out.reserve(set.size());
+  size_t scan = 0;
+  std::vector<int32_t> piece, cur, nxt, blk, part_out;
+  while (out.size() < set.size()) {
+    while (done[sorted_set[scan]]) ++scan;
+    int r = sorted_set[scan];
+    int cand;
+    int dr = bfs_depth(G, r, stamp, ++tag, &cand);
+    for (;;) {
+      int cand2;
+      int dc = bfs_depth(G, cand, stamp, ++tag, &cand2);
+      if (dc > dr) { r = cand; dr = dc; cand = cand2; }
+      else break;
+    }
+    // levels of the piece
+    piece.assign(1, r);
+    level[r] = 0;
+    done[r] = 1;
+    for (size_t q = 0; q < piece.size(); ++q) {
+      int v = piece[q];
+      for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+        int u = h.colind[k];
+        if (u != v && G.has(u) && !done[u]) { done[u] = 1; level[u] = level[v] + 1; piece.push_back(u); }
+      }
+    }
+    const int depth = level[piece.back()] + 1;
+    auto is_sep = [&](int v) { return (level[v] + 1) % sep == 0 && level[v] < depth - 1; };
+    // blocks, seeded in ascending (degree, id)
+    std::vector<int32_t> seeds;
+    for (int v : piece)
+      if (!is_sep(v)) seeds.push_back(v);
+    std::sort(seeds.begin(), seeds.end(), [&](int a, int b) { return G.before(a, b); });
+    int nblk = 0;
+    for (int v0 : seeds) {
+      if (blockof[v0] >= 0) continue;
+      blk.assign(1, v0);
+      blockof[v0] = nblk;
+      for (size_t q = 0; q < blk.size(); ++q) {
+        int v = blk[q];
+        for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+          int u = h.colind[k];
+          if (u != v && G.has(u) && !is_sep(u) && blockof[u] < 0) { blockof[u] = nblk; blk.push_back(u); }
+        }
+      }
+      ++nblk;
+      rcm(h, blk, part_out);
+      out.insert(out.end(), part_out.begin(), part_out.end());
+    }
+    // separator levels, ascending
+    for (int j = sep - 1; j < depth - 1; j += sep) {
+      cur.clear();
+      for (int v : piece)
+        if (level[v] == j) cur.push_back(v);
+      rcm(h, cur, part_out);
+      out.insert(out.end(), part_out.begin(), part_out.end());
+    }
+  }
+}
+
 std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
   const int V = h.V, ns = o.nsub;
   h.ns = ns;
@@ -315,7 +400,10 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
       ring_begin = ring_end;
     }
     std::vector<int32_t> order;
-    rcm(h, set, order);
+    if (o.ordering == FSI_ORDER_1WD)
+      onewd(h, set, o.ilu_level + 3, order);  // separators beyond the kept fill level apart
+    else
+      rcm(h, set, order);
     const int m = (int)order.size();
     const int base = (int)h.lglob.size();
     for (int l = 0; l < m; ++l) loc[order[l]] = l;

@@ -97,9 +97,10 @@ def main():
     wv = counter_values(a.write_dir, "WRITE_SIZE")
     ff, wf = calib_factor(fv, nbytes), calib_factor(wv, nbytes)
     fb, wb = sweep_bytes(fv, ff), sweep_bytes(wv, wf)
-    algo = {}
+    algo, config = {}, {}
     if a.algo_bytes:
         line = json.load(open(a.algo_bytes))
+        config = {k: line["config"].get(k) for k in ("nsub", "ilu_level", "overlap", "ordering")}
         rl = line["roofline"]
         algo[rl["kernel"]] = rl["bytes_per_launch"]
         algo[rl["other_sweep"]["kernel"]] = rl["other_sweep"]["bytes_per_launch"]
@@ -117,6 +118,8 @@ def main():
     rec = dict(ilu_hip_sha256=hashlib.sha256(src).hexdigest(), copy_mib=a.copy_mib,
                fetch_scale=round(ff, 4), write_scale=round(wf, 4), kernels=kern,
                commands=dict(fetch=a.fetch_cmd, write=a.write_cmd))
+    if config:
+        rec["config"] = config  # the Schwarz configuration the counters were taken on
     with open(a.out_json, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")

@@ -96,7 +96,8 @@ def jac_rowrel(rp, ci, Vg, Vr, V):
 # ------------------------------------------------------------------------------------------
 def test_setup_integer_parity(fsi_mod):
     m, y0, g = tube_problem()
-    for opts in (dict(nsub=4, overlap=1, ilu_level=0), dict(nsub=3, overlap=2, ilu_level=2)):
+    for opts in (dict(nsub=4, overlap=1, ilu_level=0), dict(nsub=3, overlap=2, ilu_level=2),
+                 dict(nsub=4, overlap=1, ilu_level=1, ordering=1), dict(nsub=3, overlap=2, ilu_level=3, ordering=1)):
         say(f"[setup] {opts}")
         s = fsi_mod.Solver(m, PH, opts)
         o = O.Oracle(m, PH, opts)
@@ -567,14 +568,15 @@ def test_full_size_residual_parity(tree, fsi_mod):
     assert worst <= bound
 
 
-@pytest.mark.parametrize("rigid", [True, False])
-def test_tree_schwarz_parity_bench_like(fsi_mod, rigid):
+@pytest.mark.parametrize("rigid,ordering", [(True, 0), (False, 0), (False, 1)])
+def test_tree_schwarz_parity_bench_like(fsi_mod, rigid, ordering):
     """Bench-like Schwarz configuration at oracle-checkable size: the depth-1 tree cut into
     subdomains of the benchmark's size (33), ILU(3) (rows longer than one sweep task are
-    split into several); GPU and oracle factor the same matrix."""
+    split into several), RCM or 1WD subdomain ordering; GPU and oracle factor the same
+    matrix."""
     m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     g = W.dirichlet_values(m, 30.0)
-    opts = dict(nsub=33, overlap=1, ilu_level=3)
+    opts = dict(nsub=33, overlap=1, ilu_level=3, ordering=ordering)
     P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m) if rigid else None)
     y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
     P.o.jacobian(y)
@@ -589,7 +591,11 @@ def test_tree_schwarz_parity_bench_like(fsi_mod, rigid):
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     b = P.o.pc_get()
     kappa = float(max(np.linalg.cond(u) for u in b["udiag"]))
-    say(f"[tree1 rigid={rigid}] V={m.nverts} B^-1 v rel {ez:.3e}, max cond(U_kk) {kappa:.1e}")
+    if ordering:
+        a = P.g.pc_get(factors=False)
+        for k in ("sub_ptr", "sub_verts", "blk_ptr", "lrowptr", "lcolind"):
+            assert np.array_equal(a[k], b[k]), k
+    say(f"[tree1 rigid={rigid} ordering={ordering}] V={m.nverts} B^-1 v rel {ez:.3e}, max cond(U_kk) {kappa:.1e}")
     assert ez <= (1e-10 if rigid else max(1e-8, 64 * np.finfo(float).eps * kappa))
     rhs = -P.o.residual(y)
     x = P.g.vec()

@@ -398,6 +398,84 @@ def test_rcm_recovers_a_band_from_a_scrambled_tet_chain():
     assert bw == 3
 
 
+def _scrambled_tet_chain(nv, seed):
+    """Tets {i, i+1, i+2, i+3} of a chain, vertex ids scrambled; returns the mesh and the
+    vertex id of each chain position."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(nv)
+    X = np.zeros((nv, 3))
+    t = np.arange(nv)
+    X[:, 0] = t
+    X[:, 1] = (t % 4 == 1) * 1.0 + (t % 4 == 3) * 0.3
+    X[:, 2] = (t % 4 == 2) * 1.0 + (t % 4 == 3) * 0.4
+    tets = np.array([[i, i + 1, i + 2, i + 3] for i in range(nv - 3)])
+    inv = np.argsort(perm)
+    from paper_1810_04289_amd.workload import _orient, boundary_faces
+    tets_s = _orient(X[perm], inv[tets]).astype(np.int32)
+    bf, _ = boundary_faces(tets_s)
+    m = W.Mesh(X=X[perm], tets=tets_s, tet_domain=np.zeros(len(tets_s), dtype=np.int8), bfaces=bf,
+               bface_tag=np.zeros(len(bf), dtype=np.int8))
+    return m, inv
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_one_way_dissection_of_a_tet_chain(level):
+    # Chain vertex i touches i-3 .. i+3, so the BFS levels from an end are {0}, {1,2,3},
+    # {4,5,6}, ...  With separators every level + 3 levels, the order must be: the bands
+    # between separator levels, each contiguous, then the separator levels in ascending
+    # distance from the root end (the end of smaller vertex id: both ends have the least
+    # degree, and the search keeps the first of equally deep roots).
+    nv = 40
+    m, inv = _scrambled_tet_chain(nv, seed=5)
+    o = O.Oracle(m, PH, dict(nsub=1, overlap=0, ilu_level=level, ordering=1))
+    order = o.pc_get(False)["sub_verts"]
+    assert sorted(order.tolist()) == list(range(nv))
+    root_at_0 = inv[0] < inv[nv - 1]
+    pos_of = np.empty(nv, dtype=int)         # chain position of each vertex id
+    pos_of[inv] = np.arange(nv)
+    q = pos_of if root_at_0 else nv - 1 - pos_of
+    lev = np.where(q == 0, 0, (q + 2) // 3)  # BFS level of each vertex id
+    h = lev.max() + 1
+    sep = level + 3
+    seps = [j for j in range(h - 1) if (j + 1) % sep == 0]
+    nsep = sum(int(np.sum(lev == j)) for j in seps)
+    head, tail = order[:nv - nsep], order[nv - nsep:]
+    # separators last, level by level in ascending order
+    assert [int(lev[v]) for v in tail] == sorted(int(lev[v]) for v in tail)
+    assert sorted(set(int(lev[v]) for v in tail)) == seps
+    # blocks: the bands between separators, each contiguous in the order
+    band = np.searchsorted(np.array(seps), lev[head])  # index of the band a vertex lies in
+    runs = [band[0]] + [band[i] for i in range(1, len(band)) if band[i] != band[i - 1]]
+    assert len(runs) == len(seps) + 1 and len(set(runs)) == len(runs)
+
+
+def test_one_way_dissection_shortens_the_sweep_chain():
+    # The lower triangular factor's dependency chain (rows that must be solved one after
+    # another) is about one row per row with RCM; with 1WD it is about a block plus a
+    # separator.  On the tube's subdomains (about 7 BFS levels deep, ILU(1): separators
+    # every 4 levels) that is 221 against 351 rows, on the same vertex sets
+    m = W.tube_mesh()
+    chains = {}
+    for ordering in (0, 1):
+        o = O.Oracle(m, PH, dict(nsub=4, overlap=1, ilu_level=1, ordering=ordering))
+        pc = o.pc_get(False)
+        sp, lrp, lci, bp = pc["sub_ptr"], pc["lrowptr"], pc["lcolind"], pc["blk_ptr"]
+        depth = []
+        for s in range(len(sp) - 1):
+            n, r0 = sp[s + 1] - sp[s], sp[s]
+            rp = lrp[r0 + s:r0 + s + n + 1] - lrp[r0 + s]
+            ci = lci[bp[s]:bp[s + 1]]
+            lev = np.zeros(n, dtype=int)
+            for i in range(n):
+                lo = ci[rp[i]:rp[i + 1]]
+                lo = lo[lo < i]
+                lev[i] = 1 + (lev[lo].max() if len(lo) else 0)
+            depth.append(lev.max())
+        chains[ordering] = (depth, [sorted(pc["sub_verts"][sp[s]:sp[s + 1]]) for s in range(len(sp) - 1)])
+    assert chains[0][1] == chains[1][1]            # same vertex sets, reordered
+    assert max(chains[1][0]) < 0.75 * max(chains[0][0])
+
+
 # ------------------------------------------------------------------------------------------
 # P9: Newton-Krylov-Schwarz against brute-force dense Newton on a tiny mesh
 # ------------------------------------------------------------------------------------------
