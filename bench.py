@@ -168,6 +168,7 @@ def main():
     ap.add_argument("--precision", type=int, default=0,
                     help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the row-length rule's sweep schedule")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB three times "
                          "(reference dispatch for scaling rocprofv3 byte counters)")
@@ -215,6 +216,12 @@ def main():
     for k in range(2, 2 + args.warmup):
         st = step(k)
         log(f"[bench] warmup step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
+
+    tune = None
+    if not args.no_tune:  # sweep schedule timed on the last step's factors, outside the timed steps
+        best, us = s.pc_tune(3)
+        tune = {"best_blocks_per_task": best, "us_per_apply": {str(k): round(v, 1) for k, v in us.items()}}
+        log(f"[bench] sweep schedule: {tune}")
 
     if args.calib_copy_mib > 0:
         a = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
@@ -277,7 +284,7 @@ def main():
                    "ilu_level": args.ilu, "overlap": args.overlap, "ordering": args.ordering, "jac_lag": args.jac_lag,
                    "dt": dt, "local_blocks": sw["local_blocks"],
                    "local_rows": sw["local_rows"]},
-        "NI": NI, "LI": round(LI, 2), "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
+        "NI": NI, "LI": round(LI, 2), "sweep_schedule": tune, "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK, 4) if achieved else None,

@@ -165,6 +165,18 @@ fsi_status fsi_pc_setup(fsi_solver *s);
 /* z = B^{-1} v = sum_i (R_i^0)^T (L_i U_i)^{-1} R_i^delta v. */
 fsi_status fsi_pc_apply(fsi_solver *s, const double *v /* dev, n */, double *z /* dev, n */);
 
+/* Schedule of the Schwarz sweeps.  Every subdomain's forward and backward sweep runs in one
+ * launch per sweep, one workgroup per subdomain; rows are cut into tasks of at most mb
+ * blocks, and the kernel for mb prefetches a matching number of tasks.  The candidates are
+ * mb = 8, 16, 24 and 32; at create a rule on the longest row picks one.
+ * fsi_pc_tune (after fsi_pc_setup) times every candidate on the current factors, reps
+ * applications each after one untimed, and keeps the fastest: *best_mb (may be NULL)
+ * receives it and us[4] (may be NULL) the microseconds per application of each candidate,
+ * in the order above.  fsi_pc_select sets mb directly (ERR_ARG if not a candidate).  The
+ * schedule changes the order of floating-point sums, not the operator. */
+fsi_status fsi_pc_tune(fsi_solver *s, int32_t reps, int32_t *best_mb, double *us);
+fsi_status fsi_pc_select(fsi_solver *s, int32_t mb);
+
 /* Right-preconditioned restarted GMRES on J x = rhs from x0 = 0 (classical Gram-Schmidt
  * twice, Givens rotations).  Non-convergence is reported in st->converged, not as an
  * error. */

@@ -133,12 +133,16 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   hipEvent_t e0, e1;
   hip_ok(s, hipEventCreate(&e0), "event");
   hip_ok(s, hipEventCreate(&e1), "event");
+  // the preconditioner is bracketed by events; its time is read after the iteration's
+  // own synchronization (no extra host wait between the sweeps and the SpMV)
   auto timed_pc = [&](const double* v, double* zz) {
     hip_ok(s, hipEventRecord(e0, s->stream), "event");
     hip_ok(s, launch_pc_apply(s, v, zz), "pc_apply");
     hip_ok(s, hipEventRecord(e1, s->stream), "event");
-    hip_ok(s, hipEventSynchronize(e1), "event");
+  };
+  auto add_pc_time = [&]() {
     float ms = 0.f;
+    hip_ok(s, hipEventSynchronize(e1), "event");
     hip_ok(s, hipEventElapsedTime(&ms, e0, e1), "event");
     if (t_pc) *t_pc += ms * 1e-3;
   };
@@ -160,6 +164,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
       hip_ok(s, hipMemcpyAsync(s->pinned, s->hdev, 3 * (kMaxRestart + 8) * sizeof(double), hipMemcpyDeviceToHost,
                                s->stream), "h readback");
       sync(s);
+      add_pc_time();
       const double* ha = s->pinned;
       const double* hb = s->pinned + (kMaxRestart + 8);
       double hsum2 = 0.0;
@@ -213,6 +218,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
       hip_ok(s, launch_spmv(s, x, s->w), "spmv");
       hip_ok(s, launch_axpby(s, 1.0, b, -1.0, s->w, s->r, n), "axpby");
     }
+    add_pc_time();
   }
   hip_ok(s, launch_spmv(s, x, s->w), "spmv");
   hip_ok(s, launch_axpby(s, 1.0, b, -1.0, s->w, s->w, n), "axpby");
@@ -405,21 +411,26 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->bwd_rows = upload(s, h.bwd_rows);
   {
     // per-wavefront task lists of both sweeps (level order inside each wavefront)
-    s->sweep_mb = sweep_task_blocks(std::max(s->max_lblk, s->max_ublk));
-    const int mb = s->sweep_mb;
-    auto tasks = [&](bool bwd, const std::vector<int32_t>& sub_lvl, const std::vector<int32_t>& lvl_ptr,
-                     const std::vector<int32_t>& rows, const std::vector<int32_t>& qslot, int32_t** wtask_d,
-                     int4** task_d, int4** aux_d, int32_t** nphase_d) {
-      SweepTasks st = build_sweep_tasks(h, bwd, sub_lvl, lvl_ptr, rows, qslot, mb);
-      *wtask_d = upload(s, st.wtask);
-      *task_d = upload(s, st.task);
-      *aux_d = upload(s, st.aux);
-      *nphase_d = upload(s, st.nphase);
-    };
-    tasks(false, h.fwd_sub_lvl, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_qslot, &s->fwd_wtask, &s->fwd_task,
-          &s->fwd_task_aux, &s->fwd_nphase);
-    tasks(true, h.bwd_sub_lvl, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, &s->bwd_wtask, &s->bwd_task,
-          &s->bwd_task_aux, &s->bwd_nphase);
+    // every candidate schedule (tasks of at most mb blocks); the row-length rule picks the
+    // one used until fsi_pc_tune or fsi_pc_select chooses another
+    for (int c = 0; c < kSweepPlans; ++c) {
+      SweepPlan& P = s->plans[c];
+      P.mb = kSweepPlanMB[c];
+      auto tasks = [&](bool bwd, const std::vector<int32_t>& sub_lvl, const std::vector<int32_t>& lvl_ptr,
+                       const std::vector<int32_t>& rows, const std::vector<int32_t>& qslot, int32_t** wtask_d,
+                       int4** task_d, int4** aux_d, int32_t** nphase_d) {
+        SweepTasks st = build_sweep_tasks(h, bwd, sub_lvl, lvl_ptr, rows, qslot, P.mb);
+        *wtask_d = upload(s, st.wtask);
+        *task_d = upload(s, st.task);
+        *aux_d = upload(s, st.aux);
+        *nphase_d = upload(s, st.nphase);
+      };
+      tasks(false, h.fwd_sub_lvl, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_qslot, &P.fwd_wtask, &P.fwd_task,
+            &P.fwd_task_aux, &P.fwd_nphase);
+      tasks(true, h.bwd_sub_lvl, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, &P.bwd_wtask, &P.bwd_task,
+            &P.bwd_task_aux, &P.bwd_nphase);
+    }
+    select_plan(s, sweep_task_blocks(std::max(s->max_lblk, s->max_ublk)));
     std::vector<int32_t> lbyte(h.lslot.size());
     // a slot holds 7 values of the sweep arithmetic type (FP64, or FP32 for rounded factors)
     const int slot_bytes = 7 * (s->opts.precision == FSI_PREC_FP64 ? 8 : 4);
@@ -514,6 +525,27 @@ void prof_end(fsi_solver* s, const char* name, hipEvent_t a) {
   }
   (void)hipEventRecord(b, s->stream);
   s->prof_events.push_back(ProfEntry{name, a, b});
+}
+}  // namespace fsi
+
+namespace fsi {
+// Makes the schedule with tasks of mb blocks the one the sweeps use; false if mb is not a
+// candidate.
+bool select_plan(fsi_solver* s, int mb) {
+  for (const SweepPlan& P : s->plans)
+    if (P.mb == mb && P.fwd_task) {
+      s->sweep_mb = mb;
+      s->fwd_wtask = P.fwd_wtask;
+      s->fwd_task = P.fwd_task;
+      s->fwd_task_aux = P.fwd_task_aux;
+      s->fwd_nphase = P.fwd_nphase;
+      s->bwd_wtask = P.bwd_wtask;
+      s->bwd_task = P.bwd_task;
+      s->bwd_task_aux = P.bwd_task_aux;
+      s->bwd_nphase = P.bwd_nphase;
+      return true;
+    }
+  return false;
 }
 }  // namespace fsi
 
@@ -693,6 +725,52 @@ fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
     sync(s);
     return FSI_OK;
   }, a);
+}
+
+fsi_status fsi_pc_select(fsi_solver* s, int32_t mb) {
+  if (!s) return FSI_ERR_ARG;
+  if (!select_plan(s, mb)) {
+    s->err = "no sweep schedule with " + std::to_string(mb) + " blocks per task";
+    return FSI_ERR_ARG;
+  }
+  return FSI_OK;
+}
+
+fsi_status fsi_pc_tune(fsi_solver* s, int32_t reps, int32_t* best_mb, double* us) {
+  if (!s || reps < 1 || !s->pc_ready) return FSI_ERR_ARG;
+  struct A {
+    int reps;
+    int32_t* best;
+    double* us;
+  } a{reps, best_mb, us};
+  return guard(s, [](fsi_solver* s, void* p) {
+    A* a = (A*)p;
+    hipEvent_t e0, e1;
+    hip_ok(s, hipEventCreate(&e0), "event");
+    hip_ok(s, hipEventCreate(&e1), "event");
+    // probe input: the current residual vector (finite values); output to scratch
+    double best_t = 0.0;
+    int best = s->sweep_mb;
+    for (int c = 0; c < kSweepPlans; ++c) {
+      const int mb = s->plans[c].mb;
+      select_plan(s, mb);
+      hip_ok(s, launch_pc_apply(s, s->F, s->z), "tune warm-up");
+      hip_ok(s, hipEventRecord(e0, s->stream), "event");
+      for (int r = 0; r < a->reps; ++r) hip_ok(s, launch_pc_apply(s, s->F, s->z), "tune");
+      hip_ok(s, hipEventRecord(e1, s->stream), "event");
+      hip_ok(s, hipEventSynchronize(e1), "event");
+      float ms = 0.f;
+      hip_ok(s, hipEventElapsedTime(&ms, e0, e1), "event");
+      const double t = 1e3 * ms / a->reps;
+      if (a->us) a->us[c] = t;
+      if (c == 0 || t < best_t) best_t = t, best = mb;
+    }
+    select_plan(s, best);
+    if (a->best) *a->best = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return FSI_OK;
+  }, &a);
 }
 
 fsi_status fsi_gmres(fsi_solver* s, const double* rhs, double* x, fsi_lin_stats* st) {

@@ -86,6 +86,16 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
                              const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows,
                              const std::vector<int32_t>& qslot, int mb);
 
+// One sweep schedule: task lists of both sweeps with tasks of at most mb blocks (the kernel
+// for mb fixes the prefetch depth).  kSweepPlanMB lists the candidates.
+constexpr int kSweepPlans = 4;
+constexpr int kSweepPlanMB[kSweepPlans] = {8, 16, 24, 32};
+struct SweepPlan {
+  int mb = 0;
+  int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr, *fwd_nphase = nullptr, *bwd_nphase = nullptr;
+  int4 *fwd_task = nullptr, *bwd_task = nullptr, *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
+};
+
 struct ProfEntry {
   std::string name;
   hipEvent_t a, b;
@@ -120,8 +130,10 @@ struct fsi_solver {
   uint8_t* lowned = nullptr;
   int32_t *fwd_sub_lvl = nullptr, *fwd_lvl_ptr = nullptr, *fwd_rows = nullptr;
   int32_t *bwd_sub_lvl = nullptr, *bwd_lvl_ptr = nullptr, *bwd_rows = nullptr;
-  // sweep task lists (see SweepTasks); sweep_mb: blocks per task
+  // sweep task lists (see SweepTasks) of the selected schedule; sweep_mb: blocks per task.
+  // Every candidate schedule's lists are kept (plans), so that the tuner can switch.
   int sweep_mb = 0;
+  fsi::SweepPlan plans[fsi::kSweepPlans];
   int32_t *fwd_wtask = nullptr, *bwd_wtask = nullptr, *fwd_nphase = nullptr, *bwd_nphase = nullptr;
   int4 *fwd_task = nullptr, *bwd_task = nullptr;
   int4 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
@@ -157,6 +169,7 @@ hipError_t launch_pc_setup(fsi_solver* s);
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
 hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
+bool select_plan(fsi_solver* s, int mb);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);
 hipError_t launch_vupdate(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n);

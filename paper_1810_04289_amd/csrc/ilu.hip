@@ -570,9 +570,11 @@ static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, d
 
 template <typename S>
 static hipError_t launch_sweeps_mb(fsi_solver* s, const S* facs, const double* v, double* z) {
-  switch (s->sweep_mb) {
+  switch (s->sweep_mb) {  // the candidates of kSweepPlanMB, each with its prefetch depth
+    case 8: return launch_sweeps<S, 8, 6>(s, facs, v, z);
     case 16: return launch_sweeps<S, 16, 4>(s, facs, v, z);
     case 24: return launch_sweeps<S, 24, 3>(s, facs, v, z);
+    case 32: return launch_sweeps<S, 32, 2>(s, facs, v, z);
     default: return hipErrorInvalidValue;
   }
 }

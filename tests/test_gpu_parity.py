@@ -602,3 +602,38 @@ def test_tree_schwarz_parity_bench_like(fsi_mod, rigid, ordering):
     st = P.g.gmres(P.dev(rhs), x)
     say(f"  gmres: its {st['iters']} converged {st['converged']} rel {st['rnorm_true'] / st['rnorm0']:.2e}")
     assert st["converged"] == 1
+
+
+def test_sweep_schedules_and_tuner(fsi_mod):
+    """Every sweep schedule (tasks of 8, 16, 24 or 32 blocks; ILU(3) rows on the depth-1
+    tree are cut into up to 9 tasks at 8 blocks) applies the same preconditioner as the
+    oracle; the tuner times all four and keeps one of them."""
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    g = W.dirichlet_values(m, 30.0)
+    opts = dict(nsub=33, overlap=1, ilu_level=3)
+    P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m))
+    y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
+    P.o.jacobian(y)
+    rp, ci, Vr = P.o.jacobian_get()
+    P.g.jacobian_set(Vr)
+    P.g.pc_setup()
+    P.o.pc_setup()
+    v = np.random.default_rng(6).standard_normal(m.n)
+    zr = P.o.pc_apply(v)
+    z = P.g.vec()
+    for mb in P.g.SWEEP_MB:
+        P.g.pc_select(mb)
+        z.zero_()
+        P.g.pc_apply(P.dev(v), z)
+        ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
+        say(f"[schedule mb={mb}] B^-1 v rel {ez:.3e}")
+        assert ez <= 1e-10
+    with pytest.raises(fsi_mod.FsiError):
+        P.g.pc_select(12)
+    best, us = P.g.pc_tune(reps=3)
+    say(f"[tuner] best mb {best}, us per application {us}")
+    assert best in P.g.SWEEP_MB and all(t > 0 for t in us.values())
+    assert us[best] == min(us.values())
+    z.zero_()
+    P.g.pc_apply(P.dev(v), z)
+    assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-10 * np.linalg.norm(zr)
