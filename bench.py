@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_1810_04289_amd import workload as W  # noqa: E402
+from paper_1810_04289_amd.metrics import spmv_bytes, sweep_bytes  # noqa: E402
 
 METRIC = "sec per implicit FSI time step @1e-6 Newton rtol; SpMV/ILU HBM GB/s %peak"
 HBM_PEAK = 8000.0  # GB/s, MI355X published
@@ -35,40 +36,6 @@ HBM_PEAK = 8000.0  # GB/s, MI355X published
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def sweep_bytes(s, precision: int = 0) -> dict:
-    """Algorithmic HBM bytes of one launch of each triangular sweep of the Schwarz solve,
-    with factor entries of vb bytes (8 FP64, 4 FP32, 2 BF16) and local values of yb bytes
-    (8 FP64, else 4).
-
-    forward  (y = L^-1 R v): strict-L blocks (49 vb each) and their column slot (4 B), a
-             24 B task record per local row, the gathered FP64 input (7 doubles per local
-             row) and y written (7 yb per local row);
-    backward (x = U^-1 y): strict-U blocks and the inverted diagonal of every row (49 vb
-             each), the U column slots, the task records, y read, and the owned rows of z
-             written (7 doubles per vertex).
-    """
-    vb = {0: 8, 1: 4, 2: 2}[precision]
-    yb = 8 if precision == 0 else 4
-    pc = s.pc_get(factors=False)
-    ns = len(pc["sub_nowned"])
-    rp = pc["lrowptr"].astype(np.int64)
-    col = pc["lcolind"].astype(np.int64)
-    nL = 0
-    for k in range(ns):
-        r0 = int(pc["sub_ptr"][k]) + k          # row pointers of subdomain k start here
-        n_k = int(pc["sub_ptr"][k + 1] - pc["sub_ptr"][k])
-        ptr = rp[r0:r0 + n_k + 1]
-        b0 = int(pc["blk_ptr"][k])
-        rows = np.repeat(np.arange(n_k), np.diff(ptr))
-        nL += int(np.count_nonzero(col[b0 + ptr[0]:b0 + ptr[-1]] < rows))
-    NB = len(col)
-    R = len(pc["sub_verts"])
-    nU = NB - R - nL
-    fwd = nL * (49 * vb + 4) + 24 * R + 56 * R + 7 * yb * R
-    bwd = (nU + R) * 49 * vb + 4 * nU + 24 * R + 7 * yb * R + 56 * s.V
-    return dict(ilu_fwd=fwd, ilu_bwd=bwd, local_blocks=NB, local_rows=R, l_blocks=nL, u_blocks=nU)
 
 
 def stored_traffic(kernel: str, precision: int, config: dict):
@@ -92,11 +59,6 @@ def stored_traffic(kernel: str, precision: int, config: dict):
 
 
 ORDERING = {0: "RCM", 1: "1WD"}
-
-
-def spmv_bytes(s) -> int:
-    """Algorithmic bytes of y = J x: blocks once, column indices, row pointers, x and y once."""
-    return s.nnzb * (49 * 8 + 4) + 4 * (s.V + 1) + 2 * 7 * s.V * 8
 
 
 def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1,
@@ -169,6 +131,7 @@ def main():
                     help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the row-length rule's sweep schedule")
+    ap.add_argument("--graphs", action="store_true", help="GMRES Arnoldi steps as captured graphs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB three times "
                          "(reference dispatch for scaling rocprofv3 byte counters)")
@@ -192,11 +155,13 @@ def main():
                 gmres_maxit=600,
                 gmres_rtol=1e-3, newton_rtol=1e-6, newton_maxit=20, precision=args.precision)
     s = fsi.Solver(mesh, ph, opts)
+    if args.graphs:
+        s.set_graphs(True)
     log(f"[bench] mesh V={mesh.nverts} E={mesh.ntets} n={s.n} nnzb={s.nnzb} setup {time.perf_counter() - t0:.1f}s")
 
     dt = args.dt
     nsteps = 2 + args.warmup + args.steps
-    G = [torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak((k + 1) * dt))).to(dev) for k in range(nsteps)]
+    G = [torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak((k + 1) * dt))).to(dev) for k in range(nsteps + 1)]
     rigid = W.rigid_wall_mask(mesh)
     y_old = torch.zeros(s.n, dtype=torch.float64, device=dev)
     y = torch.empty_like(y_old)
@@ -231,7 +196,9 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    s.prof_enable(True)
+    # kernel times from HIP events over the timed steps; with graphs (whose kernels events
+    # cannot bracket) from one more, eager, step after them
+    s.prof_enable(not args.graphs)
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
@@ -242,6 +209,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     sec_per_step = elapsed / args.steps
+    if args.graphs:
+        s.prof_enable(True)
+        step(nsteps)
+        torch.cuda.synchronize()
 
     kernels = {}
     for name in ("ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid", "jac_gather",
@@ -284,7 +255,8 @@ def main():
                    "ilu_level": args.ilu, "overlap": args.overlap, "ordering": args.ordering, "jac_lag": args.jac_lag,
                    "dt": dt, "local_blocks": sw["local_blocks"],
                    "local_rows": sw["local_rows"]},
-        "NI": NI, "LI": round(LI, 2), "sweep_schedule": tune, "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
+        "NI": NI, "LI": round(LI, 2), "sweep_schedule": tune, "graphs": bool(args.graphs),
+        "kernel_times_from": "one eager step after the timed steps" if args.graphs else "the timed steps", "phases_s_per_step": {k: round(v, 5) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": dom,
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK, 4) if achieved else None,

@@ -177,6 +177,15 @@ fsi_status fsi_pc_apply(fsi_solver *s, const double *v /* dev, n */, double *z /
 fsi_status fsi_pc_tune(fsi_solver *s, int32_t reps, int32_t *best_mb, double *us);
 fsi_status fsi_pc_select(fsi_solver *s, int32_t mb);
 
+/* GMRES's inner step as captured graphs (on != 0): the preconditioner, the SpMV, both
+ * Gram-Schmidt passes and the norm of each Arnoldi step j are captured into one graph on
+ * first use and replayed afterwards, one launch instead of eleven.  Results are identical
+ * to the eager path (same kernels, same order).  Graphs are dropped when the sweep
+ * schedule changes or graphs are switched off; while kernel profiling (fsi_prof_enable) is
+ * on, GMRES runs eagerly.  In graph mode the preconditioner's time in fsi_step_stats is
+ * not measured separately.  Default off. */
+fsi_status fsi_set_graphs(fsi_solver *s, int32_t on);
+
 /* Right-preconditioned restarted GMRES on J x = rhs from x0 = 0 (classical Gram-Schmidt
  * twice, Givens rotations).  Non-convergence is reported in st->converged, not as an
  * error. */

@@ -135,16 +135,67 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   hip_ok(s, hipEventCreate(&e1), "event");
   // the preconditioner is bracketed by events; its time is read after the iteration's
   // own synchronization (no extra host wait between the sweeps and the SpMV)
+  bool pc_timed = false;
   auto timed_pc = [&](const double* v, double* zz) {
     hip_ok(s, hipEventRecord(e0, s->stream), "event");
     hip_ok(s, launch_pc_apply(s, v, zz), "pc_apply");
     hip_ok(s, hipEventRecord(e1, s->stream), "event");
+    pc_timed = true;
   };
   auto add_pc_time = [&]() {
+    if (!pc_timed) return;
     float ms = 0.f;
     hip_ok(s, hipEventSynchronize(e1), "event");
     hip_ok(s, hipEventElapsedTime(&ms, e0, e1), "event");
     if (t_pc) *t_pc += ms * 1e-3;
+    pc_timed = false;
+  };
+  // One Arnoldi step: z = B^-1 V_j, w = J z, two classical Gram-Schmidt passes against
+  // V_0..V_j (coefficients to hA, hB) and |w|^2 to hn2.  Eagerly, or as the graph captured
+  // for this j on its first use (same kernels, same order: the same results).  The
+  // preconditioner's own time is measured only when run eagerly.
+  auto arnoldi_kernels = [&](int j) -> hipError_t {
+    hipError_t e = launch_pc_apply(s, s->Vb + (size_t)j * n, s->z);
+    if (e == hipSuccess) e = launch_spmv(s, s->z, s->w);
+    if (e == hipSuccess) e = launch_mdot(s, s->Vb, j + 1, s->w, n, hA);
+    if (e == hipSuccess) e = launch_vupdate(s, s->Vb, j + 1, hA, s->w, n);
+    if (e == hipSuccess) e = launch_mdot(s, s->Vb, j + 1, s->w, n, hB);
+    if (e == hipSuccess) e = launch_vupdate(s, s->Vb, j + 1, hB, s->w, n);
+    if (e == hipSuccess) e = launch_dot_partial(s, s->w, s->w, n, hn2);
+    return e;
+  };
+  auto arnoldi_step = [&](int j) {
+    if (!s->graphs || s->prof) {
+      timed_pc(s->Vb + (size_t)j * n, s->z);
+      hip_ok(s, launch_spmv(s, s->z, s->w), "spmv");
+      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hA), "mdot");
+      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hA, s->w, n), "vupdate");
+      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hB), "mdot");
+      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hB, s->w, n), "vupdate");
+      hip_ok(s, launch_dot_partial(s, s->w, s->w, n, hn2), "norm");
+      return;
+    }
+    if (!s->arnoldi[j]) {
+      // captured on a private stream (the solver's may be the legacy default stream, which
+      // cannot capture); the graph is then launched on the solver's stream
+      if (!s->cap_stream)
+        hip_ok(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking), "capture stream");
+      hipGraph_t g = nullptr;
+      hipStream_t keep = s->stream;
+      s->stream = s->cap_stream;
+      const hipError_t eb = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+      const hipError_t e = eb == hipSuccess ? arnoldi_kernels(j) : hipSuccess;
+      const hipError_t ec = eb == hipSuccess ? hipStreamEndCapture(s->stream, &g) : hipSuccess;
+      s->stream = keep;
+      hip_ok(s, eb, "begin capture");
+      hip_ok(s, e, "captured Arnoldi step");
+      hip_ok(s, ec, "end capture");
+      const hipError_t ei = hipGraphInstantiate(&s->arnoldi[j], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) s->arnoldi[j] = nullptr;
+      hip_ok(s, ei, "instantiate");
+    }
+    hip_ok(s, hipGraphLaunch(s->arnoldi[j], s->stream), "graph launch");
   };
   while (!done) {
     const double beta = norm2(s, s->r);
@@ -153,14 +204,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
     g[0] = beta;
     int jend = -1;
     for (int j = 0; j < m; ++j) {
-      double* Vj = s->Vb + (size_t)j * n;
-      timed_pc(Vj, s->z);
-      hip_ok(s, launch_spmv(s, s->z, s->w), "spmv");
-      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hA), "mdot");
-      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hA, s->w, n), "vupdate");
-      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hB), "mdot");
-      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hB, s->w, n), "vupdate");
-      hip_ok(s, launch_dot_partial(s, s->w, s->w, n, hn2), "norm");
+      arnoldi_step(j);
       hip_ok(s, hipMemcpyAsync(s->pinned, s->hdev, 3 * (kMaxRestart + 8) * sizeof(double), hipMemcpyDeviceToHost,
                                s->stream), "h readback");
       sync(s);
@@ -531,9 +575,18 @@ void prof_end(fsi_solver* s, const char* name, hipEvent_t a) {
 namespace fsi {
 // Makes the schedule with tasks of mb blocks the one the sweeps use; false if mb is not a
 // candidate.
+void drop_graphs(fsi_solver* s) {
+  for (auto& g : s->arnoldi)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+}
+
 bool select_plan(fsi_solver* s, int mb) {
   for (const SweepPlan& P : s->plans)
     if (P.mb == mb && P.fwd_task) {
+      if (mb != s->sweep_mb) drop_graphs(s);  // captured sweeps use the old task lists
       s->sweep_mb = mb;
       s->fwd_wtask = P.fwd_wtask;
       s->fwd_task = P.fwd_task;
@@ -582,6 +635,8 @@ fsi_status fsi_create(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* 
 fsi_status fsi_destroy(fsi_solver* s) {
   if (!s) return FSI_OK;
   (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->pinned) (void)hipHostFree(s->pinned);
   for (auto& e : s->prof_events) {
@@ -725,6 +780,14 @@ fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
     sync(s);
     return FSI_OK;
   }, a);
+}
+
+fsi_status fsi_set_graphs(fsi_solver* s, int32_t on) {
+  if (!s) return FSI_ERR_ARG;
+  (void)hipStreamSynchronize(s->stream);
+  if (!on) drop_graphs(s);
+  s->graphs = on != 0;
+  return FSI_OK;
 }
 
 fsi_status fsi_pc_select(fsi_solver* s, int32_t mb) {

@@ -155,6 +155,11 @@ struct fsi_solver {
   std::vector<void*> allocs;
 
   bool prof = false;
+  // GMRES Arnoldi steps captured as graphs, one per basis index j (null until first use;
+  // dropped when the sweep schedule changes)
+  bool graphs = false;
+  hipGraphExec_t arnoldi[fsi::kMaxRestart] = {};
+  hipStream_t cap_stream = nullptr;  // where the graphs are captured
   std::vector<fsi::ProfEntry> prof_events;
   std::vector<hipEvent_t> event_pool;
 };
@@ -170,6 +175,7 @@ hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
 hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
 bool select_plan(fsi_solver* s, int mb);
+void drop_graphs(fsi_solver* s);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);
 hipError_t launch_vupdate(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n);

@@ -519,6 +519,32 @@ def perturbed_state(mesh: Mesh, y: np.ndarray, seed: int, rel: float = 0.01, dfr
     return y.ravel()
 
 
+def uneven_partition(mesh: Mesh, nsub: int, sigma: float = 0.5, seed: int = 0) -> np.ndarray:
+    """Seeded subdomains of uneven size: target sizes drawn lognormal (log-standard
+    deviation sigma), then recursive coordinate bisection that cuts each vertex set across
+    its longest extent in proportion to the summed targets of the two halves of its
+    subdomain list.  Returns part [V] (int32)."""
+    rng = np.random.default_rng(seed)
+    w = rng.lognormal(0.0, sigma, nsub)
+    part = np.zeros(mesh.nverts, dtype=np.int32)
+
+    def rec(ids, subs):
+        if len(subs) == 1:
+            part[ids] = subs[0]
+            return
+        left, right = subs[:len(subs) // 2], subs[len(subs) // 2:]
+        frac = w[left].sum() / w[subs].sum()
+        P = mesh.X[ids]
+        ax = int(np.argmax(P.max(0) - P.min(0)))
+        order = ids[np.lexsort((ids, P[:, ax]))]
+        cut = int(np.clip(round(frac * len(ids)), len(left), len(ids) - len(right)))
+        rec(order[:cut], left)
+        rec(order[cut:], right)
+
+    rec(np.arange(mesh.nverts), list(range(nsub)))
+    return part
+
+
 def physics_config1():
     """Material constants of the tube and tree workloads (cgs)."""
     return dict(rho_f=1.0, mu_f=0.035, rho_s=1.2, E_s=3.0e6, nu_s=0.45, eta_s=0.0, C_I=36.0)

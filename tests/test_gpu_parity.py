@@ -637,3 +637,50 @@ def test_sweep_schedules_and_tuner(fsi_mod):
     z.zero_()
     P.g.pc_apply(P.dev(v), z)
     assert np.linalg.norm(z.cpu().numpy() - zr) <= 1e-10 * np.linalg.norm(zr)
+
+
+def test_gmres_graph_replays_match_eager(fsi_mod):
+    """GMRES with its Arnoldi steps captured as graphs: every replay, with eager work and
+    synchronizations in between, gives exactly the eager path's iterations and solution
+    (same kernels in the same order); after a schedule change the graphs are rebuilt and
+    again match the eager path.  Also times both paths on this small problem."""
+    import time
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    g = W.dirichlet_values(m, 30.0)
+    opts = dict(nsub=33, overlap=1, ilu_level=3, gmres_maxit=600)
+    P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m))
+    y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
+    s = P.g
+    yd = P.dev(y)
+    s.jacobian(yd)
+    s.pc_setup()
+    F = s.vec()
+    s.residual(yd, F)
+    rhs = -F
+
+    def solve():
+        x = s.vec()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = s.gmres(rhs, x)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), st, time.perf_counter() - t
+
+    for mb in (24, 16):
+        s.pc_select(mb)
+        s.set_graphs(False)
+        x0, st0, t_eager = solve()
+        s.set_graphs(True)
+        times = []
+        for rep in range(3):
+            x1, st1, t1 = solve()
+            times.append(t1)
+            assert st1["iters"] == st0["iters"] and st1["converged"] == st0["converged"]
+            assert np.array_equal(x1, x0), f"schedule {mb}, replay {rep}"
+            z = s.vec()
+            s.pc_apply(F, z)             # eager work between replays
+            s.residual(yd, s.vec())
+            torch.cuda.synchronize()
+        say(f"[graphs mb={mb}] its {st0['iters']}: eager {1e3 * t_eager:.1f} ms, "
+            f"first (captures) {1e3 * times[0]:.1f} ms, replays {1e3 * times[1]:.1f} / {1e3 * times[2]:.1f} ms")
+    s.set_graphs(False)
