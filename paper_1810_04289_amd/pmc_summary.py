@@ -20,10 +20,12 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SWEEPS = {"ilu_fwd": "k_ilu_sweep<0", "ilu_bwd": "k_ilu_sweep<1"}
+# sweep kernels by their direction template argument: k_ilu_sweep<scalar, 0|1, MB, D>
+SWEEPS = {"ilu_fwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?0,"), "ilu_bwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?1,")}
 
 
 def _one(d: str, pattern: str) -> str:
@@ -56,7 +58,7 @@ def calib_factor(vals: list[tuple[str, float]], nbytes: int) -> float:
 def sweep_bytes(vals: list[tuple[str, float]], factor: float) -> dict:
     out = {}
     for name, tag in SWEEPS.items():
-        v = [x for k, x in vals if tag in k]
+        v = [x for k, x in vals if tag.search(k)]
         if v:
             out[name] = dict(dispatches=len(v), mean_kib=statistics.mean(v),
                              bytes_per_launch=statistics.mean(v) * 1024.0 / factor)
