@@ -311,8 +311,8 @@ hipError_t launch_pc_setup(fsi_solver* s) {
 // Nothing a wavefront loads from memory depends on values computed in the sweep, so the
 // sweep is a pipeline over the wavefront's task list: the task metadata arrive 64 tasks at
 // a time (one task per lane, broadcast by readlane) and the block values, the column
-// rows' LDS slots and the row's input of task t + D - 1 are requested while task t is
-// computed, into D rotating register sets.  Every task issues the same number of loads
+// rows' LDS slots and the row's input of task t + D - 1 are requested right after task t
+// is computed and its phase released, into D rotating register sets.  Every task issues the same number of loads
 // (blocks beyond the task's range read 0), so the compiler's in-order memory counter waits
 // only for the set about to be used.  A row longer than MB blocks is split into consecutive
 // tasks of at most MB blocks that carry their partial sums in registers; only the last one
@@ -434,7 +434,7 @@ __device__ __forceinline__ void task_load(TaskData<typename Value<S>::C, MB>& P,
 // acc: the row's partial sums, carried from task to task while a row continues
 template <typename C, int BWD, int MB>
 __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<C, MB>& P, const char* ybuf_c, C* ybuf,
-                                         C* scr, C* yl, double* __restrict__ z, C (&acc)[4], int r, int c) {
+                                         C* yl, double* __restrict__ z, C (&acc)[4], int r, int c) {
   const int nb = T.last - T.first;
   const int cc = c < 7 ? c : 6;
   if (!(T.flags & kTaskCont)) acc[0] = acc[1] = acc[2] = acc[3] = (C)0;
@@ -461,10 +461,7 @@ __device__ __forceinline__ void task_run(const TaskMeta& T, const TaskData<C, MB
     if (c == 0 && r < 7) yl[7 * (size_t)T.row + r] = out;
   } else {
     const C t = P.base - sum;                             // y_i - sum_j U_ij x_j
-    if (c == 0 && r < 7) scr[r] = t;
-    wave_lds_sync();
-    const C tc = scr[cc];
-    wave_lds_sync();
+    const C tc = __shfl(t, 8 * cc, 64);                   // component cc: lanes of row cc
     out = sum8<C>(P.D * tc);                              // x_i = D_i (...)
     if (c == 0 && r < 7 && T.vtx < 0) z[7 * (size_t)(T.vtx & 0x7fffffff) + r] = (double)out;
   }
@@ -488,7 +485,6 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   const int s = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  C* scr = lds + 7 * (size_t)nslots + 8 * wave;   // [8] per wavefront
   const int r = lane >> 3, c = lane & 7;
   const int e = 7 * (r < 7 ? r : 6) + (c < 7 ? c : 6);   // block entry of the lane
   const int voff = (r < 7 && c < 7) ? (int)sizeof(S) * e : kOutside;
@@ -509,6 +505,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
     TaskChunk c0 = load_chunk(task, aux, cb, te, lane);
     TaskChunk c1 = load_chunk(task, aux, cb + kStride, te, lane);
     TaskData<C, MB> buf[D];
+    // tasks tb .. tb + D - 2 in flight before the first runs; the loop keeps D - 1 ahead
 #pragma unroll
     for (int k = 0; k + 1 < D; ++k) {
       const int u = tb + k < te ? tb + k : te - 1;
@@ -523,16 +520,26 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
           cb += kStride;
           c1 = load_chunk(task, aux, cb + kStride, te, lane);
         }
-        const int u = t + D - 1 < te ? t + D - 1 : te - 1;
-        task_load<S, BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
         if (t < te) {
           const TaskMeta T = chunk_get(c0, t - cb);
           while (cur < T.phase) {
             lds_barrier();
             ++cur;
           }
-          task_run<C, BWD, MB>(T, buf[k], ybuf_c, ybuf, scr, yl, z, acc, r, c);
+          task_run<C, BWD, MB>(T, buf[k], ybuf_c, ybuf, yl, z, acc, r, c);
+          // The other wavefronts wait at the end of this phase for this one: when its next
+          // task lies in a later phase, pass that barrier before issuing the prefetch
+          // below, so that the next phase's row does not wait for the load issue.
+          const int next_phase = t + 1 < te ? __builtin_amdgcn_readlane(c0.a.y, t + 1 - cb) : nL;
+          if (next_phase > cur) {
+            lds_barrier();
+            ++cur;
+          }
         }
+        // prefetch of task t + D - 1 into the set task t - 1 used (a fixed number of loads
+        // per task, also past the end, so that every wait on the memory counter is exact)
+        const int u = t + D - 1 < te ? t + D - 1 : te - 1;
+        task_load<S, BWD, MB>(buf[(k + D - 1) % D], chunk_get(c0, u - cb), lslot, fac, v, yl, lane, voff, r);
       }
     }
   }
@@ -546,7 +553,7 @@ template <typename S, int MB, int D>
 static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, double* z) {
   using C = typename Value<S>::C;
   constexpr int NT = 64 * kSweepWaves;
-  const size_t lds = ((size_t)s->h.nslots * 7 + kSweepWaves * 8) * sizeof(C);
+  const size_t lds = (size_t)s->h.nslots * 7 * sizeof(C);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_ilu_sweep<S, 0, MB, D>,
