@@ -41,7 +41,8 @@ def log(*a):
 def stored_traffic(kernel: str, precision: int, config: dict):
     """HBM bytes per launch measured with rocprofv3 counters, if the profile on record was
     taken with the current sweep source, the same sweep precision and the same Schwarz
-    configuration (subdomains, fill level, overlap, ordering); None otherwise."""
+    configuration (subdomains, fill level, overlap, ordering, sweep schedule); None
+    otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3.json")
     try:
@@ -52,7 +53,7 @@ def stored_traffic(kernel: str, precision: int, config: dict):
     if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest() or rec.get("precision", 0) != precision:
         return None
     rec_cfg = rec.get("config", {"nsub": 256, "ilu_level": 3, "overlap": 1, "ordering": 0})
-    if any(rec_cfg.get(k) != config.get(k) for k in ("nsub", "ilu_level", "overlap", "ordering")):
+    if any(rec_cfg.get(k) != config.get(k) for k in ("nsub", "ilu_level", "overlap", "ordering", "sweep_mb")):
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k.get("hbm_bytes_per_launch")
@@ -240,7 +241,8 @@ def main():
     }
     phases = {k: float(np.mean([x[k] for x in stats])) for k in
               ("t_funceval", "t_jaceval", "t_pcsetup", "t_pcapply", "t_kspsolve")}
-    schwarz_cfg = dict(nsub=args.nsub, ilu_level=args.ilu, overlap=args.overlap, ordering=args.ordering)
+    schwarz_cfg = dict(nsub=args.nsub, ilu_level=args.ilu, overlap=args.overlap, ordering=args.ordering,
+                       sweep_mb=tune["best_blocks_per_task"] if tune else None)
     out = {
         "metric": METRIC, "value": round(sec_per_step, 5), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * sec_per_step, 2), "higher_is_better": False,

@@ -372,7 +372,9 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 struct TaskMeta {  // one task, uniform across the wavefront
-  int row, vtx, first, last, slot, phase, flags, unused;
+  // phase: when the task may run (the row's own phase for the task that finishes the row,
+  // earlier for the leading tasks of a split row); row_phase: the row's own phase
+  int row, vtx, first, last, slot, phase, flags, row_phase;
 };
 
 struct TaskChunk {  // lane j: task base + j
@@ -527,10 +529,11 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
             ++cur;
           }
           task_run<C, BWD, MB>(T, buf[k], ybuf_c, ybuf, yl, z, acc, r, c);
-          // The other wavefronts wait at the end of this phase for this one: when its next
-          // task lies in a later phase, pass that barrier before issuing the prefetch
-          // below, so that the next phase's row does not wait for the load issue.
-          const int next_phase = t + 1 < te ? __builtin_amdgcn_readlane(c0.a.y, t + 1 - cb) : nL;
+          // The other wavefronts wait at the end of this phase for this one: when the next
+          // row of this wavefront finishes in a later phase (nothing more to write in this
+          // one), pass that barrier before the prefetch below and before any leading task
+          // of that row, so that the next phase's row waits for neither.
+          const int next_phase = t + 1 < te ? __builtin_amdgcn_readlane(c0.a.w, t + 1 - cb) : nL;
           if (next_phase > cur) {
             lds_barrier();
             ++cur;

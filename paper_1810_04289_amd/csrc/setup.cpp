@@ -579,8 +579,13 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
     b0 = bwd ? h.ldiag[i] + 1 : h.lrowptr[i];
     b1 = bwd ? h.lrowptr[i + 1] : h.ldiag[i];
   };
+  // level (phase) of every local row in this sweep, filled per subdomain below
+  std::vector<int32_t> lvl_of(h.lglob.size(), 0);
   // blocks [f, l) of row rows[q] on wavefront w, as tasks of at most mb blocks; the final
-  // task, which in the backward sweep is the one starting at f, finishes the row
+  // task, which in the backward sweep is the one starting at f, finishes the row.  Only the
+  // final task writes (the row's LDS slot, its output), so only it must wait for the row's
+  // own phase; an earlier task waits just for the rows it reads -- one phase past the
+  // latest of them -- and so runs while the wavefront would otherwise sit at barriers.
   auto emit = [&](int w, int q, int f, int l, int phase) {
     const int i = rows[q];
     const int g = h.lglob[i] | (h.lowned[i] ? (int)0x80000000u : 0);
@@ -589,8 +594,13 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
       const int k = bwd ? nc - 1 - c : c;
       const int cf = f + k * mb, cl = std::min(l, cf + mb);
       const int flags = (c > 0 ? kTaskCont : 0) | (c + 1 < nc ? kTaskMore : 0);
+      int ph = phase;
+      if (c + 1 < nc) {
+        ph = 0;
+        for (int p = cf; p < cl; ++p) ph = std::max(ph, lvl_of[h.lcol[p]] + 1);
+      }
       wt[w].push_back(make_int4(i, g, cf, cl));
-      wa[w].push_back(make_int4(c + 1 < nc ? -1 : qslot[q], phase, flags, 0));
+      wa[w].push_back(make_int4(c + 1 < nc ? -1 : qslot[q], ph, flags, phase));
     }
   };
   for (int sd = 0; sd < h.ns; ++sd) {
@@ -601,6 +611,8 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
     // rows go to the wavefronts round-robin over the whole schedule, not per level: with
     // about one row per level, consecutive levels then fall to different wavefronts, and
     // each wavefront issues its next prefetch while the others work
+    for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L)
+      for (int q = lvl_ptr[L]; q < lvl_ptr[L + 1]; ++q) lvl_of[rows[q]] = L - sub_lvl[sd];
     int ph = 0, next = 0;
     for (int L = sub_lvl[sd]; L < sub_lvl[sd + 1]; ++L, ++ph)
       for (int q = lvl_ptr[L]; q < lvl_ptr[L + 1]; ++q) {

@@ -24,8 +24,17 @@ import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# sweep kernels by their direction template argument: k_ilu_sweep<scalar, 0|1, MB, D>
-SWEEPS = {"ilu_fwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?0,"), "ilu_bwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?1,")}
+# sweep kernels by their template arguments: k_ilu_sweep<scalar, 0|1 (direction), MB, D>;
+# sweep_patterns(mb) keeps only the schedule with mb blocks per task (None: any)
+
+
+def sweep_patterns(mb=None):
+    m = r"\d+" if mb is None else str(int(mb))
+    return {"ilu_fwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?0, " + m + ","),
+            "ilu_bwd": re.compile(r"k_ilu_sweep<(?:[^,<>]+, )?1, " + m + ",")}
+
+
+SWEEPS = sweep_patterns()
 
 
 def _one(d: str, pattern: str) -> str:
@@ -55,9 +64,9 @@ def calib_factor(vals: list[tuple[str, float]], nbytes: int) -> float:
     return statistics.median(other) * 1024.0 / nbytes
 
 
-def sweep_bytes(vals: list[tuple[str, float]], factor: float) -> dict:
+def sweep_bytes(vals: list[tuple[str, float]], factor: float, pats=None) -> dict:
     out = {}
-    for name, tag in SWEEPS.items():
+    for name, tag in (pats or SWEEPS).items():
         v = [x for k, x in vals if tag.search(k)]
         if v:
             out[name] = dict(dispatches=len(v), mean_kib=statistics.mean(v),
@@ -98,16 +107,21 @@ def main():
     fv = counter_values(a.fetch_dir, "FETCH_SIZE")
     wv = counter_values(a.write_dir, "WRITE_SIZE")
     ff, wf = calib_factor(fv, nbytes), calib_factor(wv, nbytes)
-    fb, wb = sweep_bytes(fv, ff), sweep_bytes(wv, wf)
-    algo, config = {}, {}
+    algo, config, mb = {}, {}, None
     if a.algo_bytes:
         line = json.load(open(a.algo_bytes))
         config = {k: line["config"].get(k) for k in ("nsub", "ilu_level", "overlap", "ordering")}
+        # the schedule the timed steps ran: the tuner's choice (the tuner's trial launches of
+        # the other schedules are left out)
+        mb = (line.get("sweep_schedule") or {}).get("best_blocks_per_task")
+        config["sweep_mb"] = mb
         rl = line["roofline"]
         algo[rl["kernel"]] = rl["bytes_per_launch"]
         algo[rl["other_sweep"]["kernel"]] = rl["other_sweep"]["bytes_per_launch"]
+    pats = sweep_patterns(mb)
+    fb, wb = sweep_bytes(fv, ff, pats), sweep_bytes(wv, wf, pats)
     kern = {}
-    for k in SWEEPS:
+    for k in pats:
         if k in fb and k in wb:
             kern[k] = dict(fetch_bytes_per_launch=round(fb[k]["bytes_per_launch"]),
                            write_bytes_per_launch=round(wb[k]["bytes_per_launch"]),
