@@ -482,23 +482,58 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->lslot = upload(s, lbyte);
   }
   {
-    // factorization groups: per pivot, U_k in runs of up to 2*kFacHalf blocks
-    std::vector<int32_t> gptr(1, 0);
+    // factorization groups: per pivot, U_k in runs of up to 2*kFacHalf blocks, each with the
+    // forward level of its pivot row
+    std::vector<int32_t> lvl_of(h.lglob.size(), 0);
+    for (int sd = 0; sd < h.ns; ++sd)
+      for (int L = h.fwd_sub_lvl[sd]; L < h.fwd_sub_lvl[sd + 1]; ++L)
+        for (int q = h.fwd_lvl_ptr[L]; q < h.fwd_lvl_ptr[L + 1]; ++q) lvl_of[h.fwd_rows[q]] = L - h.fwd_sub_lvl[sd];
+    std::vector<int32_t> gptr(1, 0), glvl;
     std::vector<int4> grp;
     for (size_t i = 0; i + 1 < h.kent_ptr.size(); ++i) {
       for (int k = h.kent_ptr[i]; k < h.kent_ptr[i + 1]; ++k) {
         const int pik = h.piv[4 * k], dk = h.piv[4 * k + 1], nu = h.piv[4 * k + 2], mo = h.piv[4 * k + 3];
         const int run = 2 * kFacHalf;
         const int ngk = std::max(1, (nu + run - 1) / run);
+        const int plev = lvl_of[h.lcol[h.lrowptr[i] + pik]];
         for (int g = 0; g < ngk; ++g) {
           const int nb = std::min(run, nu - run * g);
           grp.push_back(make_int4(dk + 1 + run * g, dk, mo + run * g, (pik << 6) | (std::max(nb, 0) << 1) | (g == 0)));
+          glvl.push_back(plev);
         }
       }
       gptr.push_back((int32_t)grp.size());
     }
     s->fgrp_ptr = upload(s, gptr);
     s->fgrp = upload(s, grp);
+    s->fgrp_lvl = upload(s, glvl);
+    // rows round-robin over the factorization's wavefronts, in level order
+    s->fac_nw = fac_waves(s->max_rowblk);
+    if (s->fac_nw < 1) {
+      s->err = "a local row is too long to stage in LDS for the factorization";
+      return FSI_ERR_ARG;
+    }
+    std::vector<int32_t> wptr(1, 0), wrow, wlvl;
+    std::vector<std::vector<int32_t>> lr(s->fac_nw), ll(s->fac_nw);
+    for (int sd = 0; sd < h.ns; ++sd) {
+      for (auto& v : lr) v.clear();
+      for (auto& v : ll) v.clear();
+      int next = 0;
+      for (int L = h.fwd_sub_lvl[sd]; L < h.fwd_sub_lvl[sd + 1]; ++L)
+        for (int q = h.fwd_lvl_ptr[L]; q < h.fwd_lvl_ptr[L + 1]; ++q) {
+          lr[next % s->fac_nw].push_back(h.fwd_rows[q]);
+          ll[next % s->fac_nw].push_back(L - h.fwd_sub_lvl[sd]);
+          ++next;
+        }
+      for (int w = 0; w < s->fac_nw; ++w) {
+        wrow.insert(wrow.end(), lr[w].begin(), lr[w].end());
+        wlvl.insert(wlvl.end(), ll[w].begin(), ll[w].end());
+        wptr.push_back((int32_t)wrow.size());
+      }
+    }
+    s->fw_ptr = upload(s, wptr);
+    s->fw_row = upload(s, wrow);
+    s->fw_lvl = upload(s, wlvl);
   }
   s->umap = upload(s, h.umap);
   s->sub_row_off = upload(s, h.sub_row_off);

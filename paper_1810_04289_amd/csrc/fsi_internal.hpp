@@ -143,6 +143,12 @@ struct fsi_solver {
   // {first U block, D_k block, map offset, (position of A_ik << 6) | (blocks << 1) | first run}
   int32_t *fgrp_ptr = nullptr, *umap = nullptr;
   int4* fgrp = nullptr;
+  // fgrp_lvl[g]: forward level of group g's pivot row.  The factorization's rows go to its
+  // fac_nw wavefronts round-robin in level order: wavefront w of subdomain s factors rows
+  // fw_row[fw_ptr[s*fac_nw + w] ..] (levels fw_lvl[..])
+  int32_t* fgrp_lvl = nullptr;
+  int fac_nw = 0;
+  int32_t *fw_ptr = nullptr, *fw_row = nullptr, *fw_lvl = nullptr;
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
   void* facs = nullptr;  // FP32 or BF16 copy of fac for the sweeps (precision 1 or 2)
@@ -175,6 +181,8 @@ hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
 hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
 bool select_plan(fsi_solver* s, int mb);
+// wavefronts of the factorization (each stages one row of up to max_rowblk blocks in LDS)
+int fac_waves(int max_rowblk);
 void drop_graphs(fsi_solver* s);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);

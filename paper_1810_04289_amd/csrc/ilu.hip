@@ -103,23 +103,37 @@ __device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bo
     G.pos[h] = (int)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (lane / 7) + 4 * kFacHalf * h, 0, 0);
 }
 
-// Factorization of one subdomain per workgroup, one row per wavefront, block IKJ order.
-// The row being factored is staged in the wavefront's LDS slice (maxrow blocks).  Its
-// work is a list of groups built on the host: for each pivot k (ascending), U_k in groups
-// of up to 18 blocks (one group if U_k is empty).  The first group of a pivot forms
+// Factorization of one subdomain per workgroup, block IKJ order, one row at a time per
+// wavefront.  The row being factored is staged in the wavefront's LDS slice (maxrow blocks).
+// Its work is a list of groups built on the host: for each pivot k (ascending), U_k in
+// groups of up to 18 blocks (one group if U_k is empty).  The first group of a pivot forms
 // L_ik = A_ik D_k with lane e < 49 holding entry e, writes it back and reads it into every
 // lane; each group then applies A_ij -= L_ik U_kj to its blocks, lane q < 63 holding column
 // q % 7 of blocks q / 7 and 9 + q / 7 (98 FMAs and 14 LDS read-modify-writes per lane).
-// U_k and D_k are final rows of earlier levels and each group's blocks are contiguous, so
-// the loads of group t + P - 1 are issued while group t computes, into P rotating register
-// sets; the group descriptors arrive 64 at a time, one per lane, broadcast by readlane.
+// Each group's blocks are contiguous, so the loads of group t + P - 1 are issued while
+// group t computes, into P rotating register sets; the group descriptors arrive 64 at a
+// time, one per lane, broadcast by readlane.
+//
+// Schedule.  The rows go to the wavefronts round-robin in level order, and a row is worked
+// on before its own level: a group may start once its pivot row is final, that is once the
+// workgroup has passed the barrier that ends the pivot's level (cur counts the barriers a
+// wavefront has passed).  A row's last pivots are usually rows of the levels just before
+// it, so most of its groups run early, while another wavefront finishes the current level.
+// So as not to hold that level back, a wavefront working ahead passes a barrier after a
+// share of its row's remaining groups (spread over the levels left before the row is due);
+// after writing a row back it passes the barrier of the row's level at once (after the
+// last of its rows of that level, when a level has more rows than wavefronts).  Every
+// wavefront passes exactly one barrier per level, and a row is written back before its
+// level's barrier, so a reader that waits for cur > level(k) sees row k final.
 template <int NT, int P>
-__global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ sub_lvl,
-                                                   const int32_t* __restrict__ lvl_ptr,
-                                                   const int32_t* __restrict__ rows,
+__global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ nphase,
+                                                   const int32_t* __restrict__ fw_ptr,
+                                                   const int32_t* __restrict__ fw_row,
+                                                   const int32_t* __restrict__ fw_lvl,
                                                    const int32_t* __restrict__ lrowptr,
                                                    const int32_t* __restrict__ fgrp_ptr,
                                                    const int4* __restrict__ fgrp,
+                                                   const int32_t* __restrict__ fgrp_lvl,
                                                    const int32_t* __restrict__ umap,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
@@ -138,157 +152,196 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ s
   const int voff_d = owner ? 8 * ent : kOutside;
   double* row = lds + (size_t)wave * (maxrow * 49 + 56);
   double* dsc = row + (size_t)maxrow * 49;  // D_k of the current pivot
-  const int L0 = sub_lvl[s], L1 = sub_lvl[s + 1];
-  for (int L = L0; L < L1; ++L) {
-    const int r1 = lvl_ptr[L + 1];
-    for (int q = lvl_ptr[L] + wave; q < r1; q += NW) {
-      // row metadata is uniform across the wavefront: keep it in scalar registers
-      const int i = __builtin_amdgcn_readfirstlane(rows[q]);
-      const int rb = __builtin_amdgcn_readfirstlane(lrowptr[i]);
-      const int nbe = (__builtin_amdgcn_readfirstlane(lrowptr[i + 1]) - rb) * 49;
-      const size_t gb = (size_t)rb * 49;
-      const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
-      const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
-      // c0 holds groups [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
-      // P - 1 groups, so group t and group t + P - 1 loaded with it always share c0
-      constexpr int kStride = 64 - (P - 1);
-      auto chunk = [&](int t) { return fgrp[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
-      int cb = 0;
-      int4 c0 = chunk(0), c1 = chunk(kStride);
-      // stage the row: all loads of a round issued before its LDS writes
-      for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
-        double tmp[8];
+  const int nL = nphase[s];
+  const int wb = fw_ptr[s * NW + wave], we = fw_ptr[s * NW + wave + 1];
+  int cur = 0;  // level barriers passed
+  // barrier with workgroup-scope ordering of global memory as well as LDS: rows are read
+  // back from global memory by the other wavefronts
+  auto level_barrier = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    ++cur;
+  };
+  for (int rw = wb; rw < we; ++rw) {
+    // row metadata is uniform across the wavefront: keep it in scalar registers
+    const int i = __builtin_amdgcn_readfirstlane(fw_row[rw]);
+    const int Li = __builtin_amdgcn_readfirstlane(fw_lvl[rw]);
+    const int rb = __builtin_amdgcn_readfirstlane(lrowptr[i]);
+    const int nbe = (__builtin_amdgcn_readfirstlane(lrowptr[i + 1]) - rb) * 49;
+    const size_t gb = (size_t)rb * 49;
+    const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
+    const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
+    // c0 holds groups [cb, cb + 64) (descriptors, and pivot levels in v0) and c1 / v1 the
+    // next chunk; consecutive chunks overlap by P - 1 groups, so group t and group t + P - 1
+    // loaded with it always share c0
+    constexpr int kStride = 64 - (P - 1);
+    auto chunk = [&](int t) { return fgrp[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
+    auto lchunk = [&](int t) { return fgrp_lvl[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
+    int cb = 0;
+    int4 c0 = chunk(0), c1 = chunk(kStride);
+    int v0 = lchunk(0), v1 = lchunk(kStride);
+    // stage the row: all loads of a round issued before its LDS writes
+    for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+      double tmp[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = e0 + lane + 64 * u;
-          tmp[u] = fac[gb + (e < nbe ? e : nbe - 1)];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = e0 + lane + 64 * u;
-          if (e < nbe) row[e] = tmp[u];
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + lane + 64 * u;
+        tmp[u] = fac[gb + (e < nbe ? e : nbe - 1)];
       }
-      wave_lds_sync();
-      double lrow[7][7];  // L_ik of the current pivot, all entries in every lane
-      auto consume = [&](const FacGroup& G, const FacDesc& F) {
-        const int pik = F.flags >> 6;
-        if (F.flags & 1) {  // first group of the pivot: L_ik = A_ik D_k
-          if (owner) dsc[ent] = G.d;
-          wave_lds_sync();
-          double l = 0.0;
 #pragma unroll
-          for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
-          wave_lds_sync();
-          if (owner) row[pik * 49 + ent] = l;
-          wave_lds_sync();
-#pragma unroll
-          for (int r = 0; r < 7; ++r)
-#pragma unroll
-            for (int m = 0; m < 7; ++m) lrow[r][m] = row[pik * 49 + 7 * r + m];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {  // A_ij -= L_ik U_kj, column qc
-          double acc[7];
-#pragma unroll
-          for (int r = 0; r < 7; ++r) {
-            acc[r] = 0.0;
-#pragma unroll
-            for (int m = 0; m < 7; ++m) acc[r] += lrow[r][m] * G.u[h][m];
-          }
-          if (qlane && G.pos[h] > 0) {
-            double* a = row + (G.pos[h] - 1) * 49 + qc;
-#pragma unroll
-            for (int r = 0; r < 7; ++r) a[7 * r] -= acc[r];
-          }
-        }
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + lane + 64 * u;
+        if (e < nbe) row[e] = tmp[u];
+      }
+    }
+    wave_lds_sync();
+    double lrow[7][7];  // L_ik of the current pivot, all entries in every lane
+    auto consume = [&](const FacGroup& G, const FacDesc& F) {
+      const int pik = F.flags >> 6;
+      if (F.flags & 1) {  // first group of the pivot: L_ik = A_ik D_k
+        if (owner) dsc[ent] = G.d;
         wave_lds_sync();
-      };
-      if (ng > 0) {
-        FacGroup buf[P];
+        double l = 0.0;
 #pragma unroll
-        for (int k = 0; k + 1 < P; ++k) {
-          const int u = k < ng ? k : ng - 1;
-          fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, umap, voff_u, voff_d, lane);
+        for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
+        wave_lds_sync();
+        if (owner) row[pik * 49 + ent] = l;
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 7; ++r)
+#pragma unroll
+          for (int m = 0; m < 7; ++m) lrow[r][m] = row[pik * 49 + 7 * r + m];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {  // A_ij -= L_ik U_kj, column qc
+        double acc[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          acc[r] = 0.0;
+#pragma unroll
+          for (int m = 0; m < 7; ++m) acc[r] += lrow[r][m] * G.u[h][m];
         }
-        for (int t0 = 0; t0 < ng; t0 += P) {
+        if (qlane && G.pos[h] > 0) {
+          double* a = row + (G.pos[h] - 1) * 49 + qc;
 #pragma unroll
-          for (int k = 0; k < P; ++k) {
-            const int t = t0 + k;
-            if (t < ng && t + P - 1 - cb == 64) {  // the chunk at cb + kStride starts at group t
-              c0 = c1;
-              cb += kStride;
-              c1 = chunk(cb + kStride);
-            }
-            const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
-            fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, umap, voff_u, voff_d,
-                           lane);
-            if (t < ng) consume(buf[k], desc_get(c0, t - cb));
+          for (int r = 0; r < 7; ++r) a[7 * r] -= acc[r];
+        }
+      }
+      wave_lds_sync();
+    };
+    if (ng > 0) {
+      // work ahead of the row's level in shares: at most `budget` groups between barriers
+      int done = 0;
+      auto share = [&](int left) { const int lv = Li - cur + 1; return lv > 1 ? (left + lv - 1) / lv : left; };
+      int budget = share(ng);
+      FacGroup buf[P];
+#pragma unroll
+      for (int k = 0; k + 1 < P; ++k) {
+        const int u = k < ng ? k : ng - 1;
+        const int lu = __builtin_amdgcn_readlane(v0, u - cb);
+        while (cur <= lu) level_barrier();  // pivot row final before its blocks are read
+        fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, umap, voff_u, voff_d, lane);
+      }
+      for (int t0 = 0; t0 < ng; t0 += P) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          const int t = t0 + k;
+          if (t < ng && t + P - 1 - cb == 64) {  // the chunk at cb + kStride starts at group t
+            c0 = c1;
+            v0 = v1;
+            cb += kStride;
+            c1 = chunk(cb + kStride);
+            v1 = lchunk(cb + kStride);
           }
-        }
-      }
-      // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
-      const int pd = (__builtin_amdgcn_readfirstlane(ldiag[i]) - rb) * 49;
-      double M = row[pd + ent];
-      if (owner) udiag[49 * (size_t)i + ent] = M;
-      double Iv = (rr == cc) ? 1.0 : 0.0;
-      bool bad = false;
-      for (int p = 0; p < 7; ++p) {
-        double colv[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) colv[m] = __shfl(M, m * 7 + p, 64);
-        int pr = p;
-        double best = fabs(colv[p]);
-        for (int m = p + 1; m < 7; ++m)
-          if (fabs(colv[m]) > best) { best = fabs(colv[m]); pr = m; }
-        if (!(best > 0.0) || !isfinite(best)) bad = true;
-        const int srow = (rr == p) ? pr : (rr == pr ? p : rr);
-        M = __shfl(M, srow * 7 + cc, 64);
-        Iv = __shfl(Iv, srow * 7 + cc, 64);
-        const double pv = __shfl(M, p * 7 + p, 64);
-        if (rr == p) { M = M / pv; Iv = Iv / pv; }
-        const double fct = __shfl(M, rr * 7 + p, 64);
-        const double Mp = __shfl(M, p * 7 + cc, 64), Ip = __shfl(Iv, p * 7 + cc, 64);
-        if (rr != p) { M = M - fct * Mp; Iv = Iv - fct * Ip; }
-      }
-      if (bad && lane == 0) atomicOr(&flags[1], 1);
-      wave_lds_sync();
-      if (owner) row[pd + ent] = Iv;
-      wave_lds_sync();
-      for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
-        double tmp[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = e0 + lane + 64 * u;
-          tmp[u] = row[e < nbe ? e : nbe - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = e0 + lane + 64 * u;
-          if (e < nbe) fac[gb + e] = tmp[u];
+          const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
+          const int lu = __builtin_amdgcn_readlane(v0, u - cb);
+          while (cur <= lu) level_barrier();
+          fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, umap, voff_u, voff_d,
+                         lane);
+          if (t < ng) {
+            consume(buf[k], desc_get(c0, t - cb));
+            if (cur < Li && ++done >= budget) {  // ahead of the row's level: let the level go on
+              level_barrier();
+              done = 0;
+              budget = share(ng - t - 1);
+            }
+          }
         }
       }
     }
-    __syncthreads();
+    // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
+    const int pd = (__builtin_amdgcn_readfirstlane(ldiag[i]) - rb) * 49;
+    double M = row[pd + ent];
+    if (owner) udiag[49 * (size_t)i + ent] = M;
+    double Iv = (rr == cc) ? 1.0 : 0.0;
+    bool bad = false;
+    for (int p = 0; p < 7; ++p) {
+      double colv[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) colv[m] = __shfl(M, m * 7 + p, 64);
+      int pr = p;
+      double best = fabs(colv[p]);
+      for (int m = p + 1; m < 7; ++m)
+        if (fabs(colv[m]) > best) { best = fabs(colv[m]); pr = m; }
+      if (!(best > 0.0) || !isfinite(best)) bad = true;
+      const int srow = (rr == p) ? pr : (rr == pr ? p : rr);
+      M = __shfl(M, srow * 7 + cc, 64);
+      Iv = __shfl(Iv, srow * 7 + cc, 64);
+      const double pv = __shfl(M, p * 7 + p, 64);
+      if (rr == p) { M = M / pv; Iv = Iv / pv; }
+      const double fct = __shfl(M, rr * 7 + p, 64);
+      const double Mp = __shfl(M, p * 7 + cc, 64), Ip = __shfl(Iv, p * 7 + cc, 64);
+      if (rr != p) { M = M - fct * Mp; Iv = Iv - fct * Ip; }
+    }
+    if (bad && lane == 0) atomicOr(&flags[1], 1);
+    wave_lds_sync();
+    if (owner) row[pd + ent] = Iv;
+    wave_lds_sync();
+    for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+      double tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + lane + 64 * u;
+        tmp[u] = row[e < nbe ? e : nbe - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + lane + 64 * u;
+        if (e < nbe) fac[gb + e] = tmp[u];
+      }
+    }
+    // release: the row is final; pass the barrier that ends its level, unless this
+    // wavefront's next row is of the same level (then that row releases it)
+    const int next_lvl = rw + 1 < we ? __builtin_amdgcn_readfirstlane(fw_lvl[rw + 1]) : nL;
+    if (next_lvl > Li)
+      while (cur <= Li) level_barrier();
   }
+  while (cur < nL) level_barrier();  // every wavefront passes the same number of barriers
+}
+
+int fac_waves(int max_rowblk) {
+  const size_t per_wave = ((size_t)max_rowblk * 49 + 56) * sizeof(double);
+  return (int)std::min<size_t>(4, (160 * 1024) / per_wave);
 }
 
 hipError_t launch_pc_setup(fsi_solver* s) {
   if (s->NB == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ilu_gather, dim3(nblk(s->NB * 49, 256)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
                      s->fac);
-  // up to four row-staging wavefronts per workgroup, as many as the longest row allows
+  // up to four row-staging wavefronts per workgroup, as many as the longest row allows (the
+  // rows were dealt to that many wavefronts at create)
   const size_t per_wave = ((size_t)s->max_rowblk * 49 + 56) * sizeof(double);
-  const int waves = (int)std::min<size_t>(4, (160 * 1024) / per_wave);
-  if (waves < 1) return hipErrorInvalidConfiguration;  // a row too long to stage in LDS
+  const int waves = s->fac_nw;
+  if (waves < 1 || waves != fac_waves(s->max_rowblk)) return hipErrorInvalidConfiguration;
   const size_t lds = per_wave * waves;
   auto go = [&](auto kern, int nt) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     FSI_PROF_LAUNCH(s, "ilu_factor",
-                    hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_sub_lvl, s->fwd_lvl_ptr,
-                                       s->fwd_rows, s->lrowptr, s->fgrp_ptr, s->fgrp, s->umap, s->ldiag, s->fac,
-                                       s->udiag, s->flags, s->max_rowblk));
+                    hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
+                                       s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
+                                       s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk));
     return hipSuccess;
   };
   constexpr int P = kFacDepth;
