@@ -683,4 +683,13 @@ def test_gmres_graph_replays_match_eager(fsi_mod):
             torch.cuda.synchronize()
         say(f"[graphs mb={mb}] its {st0['iters']}: eager {1e3 * t_eager:.1f} ms, "
             f"first (captures) {1e3 * times[0]:.1f} ms, replays {1e3 * times[1]:.1f} / {1e3 * times[2]:.1f} ms")
+    # a whole Newton step in graph mode equals the eager one, iteration for iteration
+    sols = {}
+    for on in (False, True):
+        s.set_graphs(on)
+        yn = P.dev(y)
+        st, rc = s.newton_solve(yn)
+        assert rc == 0
+        sols[on] = (yn.cpu().numpy(), st["newton_iters"], st["lin_hist"][:st["newton_iters"]])
+    assert sols[True][1:] == sols[False][1:] and np.array_equal(sols[True][0], sols[False][0])
     s.set_graphs(False)
