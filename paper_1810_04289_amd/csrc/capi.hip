@@ -59,13 +59,18 @@ void clear_flags(fsi_solver* s) {
   hip_ok(s, hipMemsetAsync(s->flags, 0, 4 * sizeof(int32_t), s->stream), "memset flags");
 }
 
-int32_t read_flag(fsi_solver* s, int which) {
-  int32_t v = 0;
+// the four device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound
+void read_flags(fsi_solver* s, int32_t out[4]) {
   hip_ok(s, hipMemcpyAsync(&s->pinned[200], s->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
          "flag readback");
   sync(s);
-  std::memcpy(&v, (char*)&s->pinned[200] + 4 * which, 4);
-  return v;
+  std::memcpy(out, &s->pinned[200], 4 * sizeof(int32_t));
+}
+
+int32_t read_flag(fsi_solver* s, int which) {
+  int32_t v[4];
+  read_flags(s, v);
+  return v[which];
 }
 
 fsi_status residual_impl(fsi_solver* s, const double* y, double* F) {
@@ -98,7 +103,13 @@ fsi_status pc_setup_impl(fsi_solver* s) {
   clear_flags(s);
   hip_ok(s, launch_pc_setup(s), "pc_setup");
   hip_ok(s, launch_fac_round(s), "factor rounding");
-  if (read_flag(s, 1)) {
+  int32_t f[4];
+  read_flags(s, f);
+  if (f[2]) {
+    s->err = "a subdomain factorization waited on a pivot row beyond its bound";
+    return FSI_ERR_HIP;
+  }
+  if (f[1]) {
     s->err = "zero pivot in a subdomain factorization";
     return FSI_ERR_ZERO_PIVOT;
   }

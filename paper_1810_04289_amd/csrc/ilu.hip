@@ -68,6 +68,8 @@ __device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int vo
 }
 
 constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
+constexpr int kFacSpinLimit = 1 << 23;  // polls of a factorization wait before it gives up
+constexpr int kWaitVmcnt0 = 0x0F70;     // s_waitcnt operand: vmcnt(0), other counters free
 
 struct FacDesc {  // one factorization group, uniform across the wavefront (see fsi_internal.hpp)
   int ublock, dk, moff, flags;
@@ -114,17 +116,16 @@ __device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bo
 // group t computes, into P rotating register sets; the group descriptors arrive 64 at a
 // time, one per lane, broadcast by readlane.
 //
-// Schedule.  The rows go to the wavefronts round-robin in level order, and a row is worked
-// on before its own level: a group may start once its pivot row is final, that is once the
-// workgroup has passed the barrier that ends the pivot's level (cur counts the barriers a
-// wavefront has passed).  A row's last pivots are usually rows of the levels just before
-// it, so most of its groups run early, while another wavefront finishes the current level.
-// So as not to hold that level back, a wavefront working ahead passes a barrier after a
-// share of its row's remaining groups (spread over the levels left before the row is due);
-// after writing a row back it passes the barrier of the row's level at once (after the
-// last of its rows of that level, when a level has more rows than wavefronts).  Every
-// wavefront passes exactly one barrier per level, and a row is written back before its
-// level's barrier, so a reader that waits for cur > level(k) sees row k final.
+// Schedule.  The rows go to the wavefronts round-robin in level order, and each wavefront
+// works through its rows as far ahead as their pivots allow: a group may start once its
+// pivot row is final.  There are no level barriers.  Each wavefront publishes in LDS a
+// progress level p_w such that all of its rows below level p_w are final (the level of its
+// next unfinished row), raised after a row's write-back has completed; a group whose pivot
+// row has level l waits until min_w p_w > l.  Rows depend only on rows of lower levels, and
+// the wavefront with the smallest p_w is working on a row whose pivots are all below that
+// level, so it always proceeds: the waits cannot form a cycle.  Each wait is bounded all
+// the same; a wavefront that exceeds the bound raises an error flag and stops waiting, so
+// that the kernel still ends (with its factors marked invalid).
 template <int NT, int P>
 __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ nphase,
                                                    const int32_t* __restrict__ fw_ptr,
@@ -154,14 +155,29 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   double* dsc = row + (size_t)maxrow * 49;  // D_k of the current pivot
   const int nL = nphase[s];
   const int wb = fw_ptr[s * NW + wave], we = fw_ptr[s * NW + wave + 1];
-  int cur = 0;  // level barriers passed
-  // barrier with workgroup-scope ordering of global memory as well as LDS: rows are read
-  // back from global memory by the other wavefronts
-  auto level_barrier = [&]() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_barrier();
+  __shared__ int prog[NW];  // progress levels of the wavefronts
+  if (lane == 0) prog[wave] = wb < we ? fw_lvl[wb] : nL;
+  __syncthreads();
+  int seen = 0;      // a lower bound of min_w p_w (the levels only grow)
+  bool live = true;  // false once a wait has exceeded its bound
+  // wait until every row of level <= l is final; the acquire fence keeps the pivot row's
+  // loads after the wait
+  auto wait_final = [&](int l) {
+    if (l < seen || !live) return;
+    for (int spins = 0;; ++spins) {
+      int m = nL;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) m = min(m, __hip_atomic_load(&prog[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+      seen = __builtin_amdgcn_readfirstlane(m);
+      if (l < seen) break;
+      if (spins == kFacSpinLimit) {
+        live = false;
+        if (lane == 0) atomicOr(&flags[2], 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    ++cur;
   };
   for (int rw = wb; rw < we; ++rw) {
     // row metadata is uniform across the wavefront: keep it in scalar registers
@@ -231,16 +247,11 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       wave_lds_sync();
     };
     if (ng > 0) {
-      // work ahead of the row's level in shares: at most `budget` groups between barriers
-      int done = 0;
-      auto share = [&](int left) { const int lv = Li - cur + 1; return lv > 1 ? (left + lv - 1) / lv : left; };
-      int budget = share(ng);
       FacGroup buf[P];
 #pragma unroll
       for (int k = 0; k + 1 < P; ++k) {
         const int u = k < ng ? k : ng - 1;
-        const int lu = __builtin_amdgcn_readlane(v0, u - cb);
-        while (cur <= lu) level_barrier();  // pivot row final before its blocks are read
+        wait_final(__builtin_amdgcn_readlane(v0, u - cb));  // pivot row final before its blocks are read
         fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, umap, voff_u, voff_d, lane);
       }
       for (int t0 = 0; t0 < ng; t0 += P) {
@@ -255,18 +266,10 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
             v1 = lchunk(cb + kStride);
           }
           const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
-          const int lu = __builtin_amdgcn_readlane(v0, u - cb);
-          while (cur <= lu) level_barrier();
+          wait_final(__builtin_amdgcn_readlane(v0, u - cb));
           fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, umap, voff_u, voff_d,
                          lane);
-          if (t < ng) {
-            consume(buf[k], desc_get(c0, t - cb));
-            if (cur < Li && ++done >= budget) {  // ahead of the row's level: let the level go on
-              level_barrier();
-              done = 0;
-              budget = share(ng - t - 1);
-            }
-          }
+          if (t < ng) consume(buf[k], desc_get(c0, t - cb));
         }
       }
     }
@@ -311,18 +314,20 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
         if (e < nbe) fac[gb + e] = tmp[u];
       }
     }
-    // release: the row is final; pass the barrier that ends its level, unless this
-    // wavefront's next row is of the same level (then that row releases it)
+    // release: once the write-back has completed, raise the progress level to the next
+    // row's level (unchanged when that row is of the same level)
     const int next_lvl = rw + 1 < we ? __builtin_amdgcn_readfirstlane(fw_lvl[rw + 1]) : nL;
-    if (next_lvl > Li)
-      while (cur <= Li) level_barrier();
+    if (next_lvl > Li) {
+      __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) __hip_atomic_store(&prog[wave], next_lvl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
   }
-  while (cur < nL) level_barrier();  // every wavefront passes the same number of barriers
 }
 
 int fac_waves(int max_rowblk) {
   const size_t per_wave = ((size_t)max_rowblk * 49 + 56) * sizeof(double);
-  return (int)std::min<size_t>(4, (160 * 1024) / per_wave);
+  return (int)std::min<size_t>(4, (160 * 1024 - 64) / per_wave);  // 64 B for the progress levels
 }
 
 hipError_t launch_pc_setup(fsi_solver* s) {
