@@ -160,7 +160,9 @@ fsi_status fsi_jacobian_set(fsi_solver *s, const double *vals /* host, nnzb*49 *
 fsi_status fsi_spmv(fsi_solver *s, const double *x /* dev, n */, double *y /* dev, n */);
 
 /* Schwarz setup (§3 eqs. (15)-(16)): gather every subdomain matrix from J and factor it
- * by block ILU(l).  Error ZERO_PIVOT on a singular pivot block. */
+ * by block ILU(l).  Error ZERO_PIVOT on a singular pivot block; error HIP if a row of the
+ * factorization waited on its pivot rows beyond a fixed bound (the factors are then invalid;
+ * a correct schedule never comes near it). */
 fsi_status fsi_pc_setup(fsi_solver *s);
 /* z = B^{-1} v = sum_i (R_i^0)^T (L_i U_i)^{-1} R_i^delta v. */
 fsi_status fsi_pc_apply(fsi_solver *s, const double *v /* dev, n */, double *z /* dev, n */);
