@@ -59,7 +59,8 @@ void clear_flags(fsi_solver* s) {
   hip_ok(s, hipMemsetAsync(s->flags, 0, 4 * sizeof(int32_t), s->stream), "memset flags");
 }
 
-// the four device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound
+// the four device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound,
+// [3] sweep wait bound
 void read_flags(fsi_solver* s, int32_t out[4]) {
   hip_ok(s, hipMemcpyAsync(&s->pinned[200], s->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
          "flag readback");
@@ -282,6 +283,10 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) *st = L;
+  if (read_flag(s, 3)) {
+    s->err = "a Schwarz sweep waited on a row beyond its bound";
+    return FSI_ERR_HIP;
+  }
   return FSI_OK;
 }
 
@@ -335,8 +340,12 @@ fsi_status newton_impl(fsi_solver* s, double* y, fsi_step_stats* st) {
     fsi_lin_stats ls{};
     t0 = now();
     double tpc = 0.0;
-    gmres_impl(s, s->rhs, s->dy, &ls, &tpc);
+    const fsi_status lrc = gmres_impl(s, s->rhs, s->dy, &ls, &tpc);
     S.t_kspsolve += now() - t0;
+    if (lrc != FSI_OK) {
+      status = lrc;
+      break;
+    }
     S.t_pcapply += tpc;
     S.linear_iters += ls.iters;
     if (k < FSI_MAX_NEWTON) S.lin_hist[k] = ls.iters;
@@ -823,7 +832,10 @@ fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
   return guard(s, [](fsi_solver* s, void* p) {
     const double** a = (const double**)p;
     hip_ok(s, launch_pc_apply(s, a[0], (double*)a[1]), "pc_apply");
-    sync(s);
+    if (read_flag(s, 3)) {
+      s->err = "a Schwarz sweep waited on a row beyond its bound";
+      return FSI_ERR_HIP;
+    }
     return FSI_OK;
   }, a);
 }

@@ -70,6 +70,7 @@ __device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int vo
 constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
 constexpr int kFacSpinLimit = 1 << 23;  // polls of a factorization wait before it gives up
 constexpr int kWaitVmcnt0 = 0x0F70;     // s_waitcnt operand: vmcnt(0), other counters free
+constexpr int kSweepSpinLimit = 1 << 23;  // polls of a sweep wait before it gives up
 
 struct FacDesc {  // one factorization group, uniform across the wavefront (see fsi_internal.hpp)
   int ublock, dk, moff, flags;
@@ -363,8 +364,16 @@ hipError_t launch_pc_setup(fsi_solver* s) {
 //
 // Level results travel through LDS: each row whose value is read later in the same sweep
 // owns an LDS slot from its level to its last reader's level (slots assigned on the host
-// by interval colouring; a few hundred slots per subdomain).  The level barrier then only
-// orders LDS traffic, so global loads stay in flight across it.
+// by interval colouring; a few hundred slots per subdomain).
+//
+// Levels (phases) are ordered without barriers.  Each wavefront publishes in LDS the phase
+// of its next unfinished row: all of its rows below that phase are finished.  A task of
+// phase p waits until every wavefront has published at least p, so the rows it reads have
+// been written; a row taking over a slot has a phase above the slot's last reader's, so
+// that reader is finished too.  The wavefront with the smallest published phase can always
+// run its next task (a task's phase never exceeds its row's), so the waits cannot form a
+// cycle; each is bounded all the same, and past the bound the wavefront sets an error flag
+// and stops waiting.  Only LDS is ordered, so global loads stay in flight across the waits.
 //
 // Nothing a wavefront loads from memory depends on values computed in the sweep, so the
 // sweep is a pipeline over the wavefront's task list: the task metadata arrive 64 tasks at
@@ -421,12 +430,6 @@ __device__ __forceinline__ C sum8(C v) {
   v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp_mov<0x141>(v);  // row_half_mirror
   return v;
-}
-
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 struct TaskMeta {  // one task, uniform across the wavefront
@@ -537,7 +540,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
                                                                const S* __restrict__ fac,
                                                                const double* __restrict__ v,
                                                                typename Value<S>::C* yl, double* __restrict__ z,
-                                                               int nslots) {
+                                                               int32_t* __restrict__ flags, int nslots) {
   using C = typename Value<S>::C;
   extern __shared__ double lds_d[];
   C* lds = (C*)lds_d;
@@ -550,11 +553,37 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   const int voff = (r < 7 && c < 7) ? (int)sizeof(S) * e : kOutside;
   const char* ybuf_c = (const char*)ybuf + sizeof(C) * (c < 7 ? c : 6);
   const int nL = nphase[s];
+  const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
+  // progress phases of the wavefronts: every row of wavefront w with a phase below prog[w]
+  // is finished (its slot written, all its reads done)
+  __shared__ int prog[kSweepWaves];
+  int mine = te > tb ? __builtin_amdgcn_readfirstlane(aux[tb].w) : nL;  // the next row's phase
+  if (lane == 0) prog[wave] = mine;
   // slots are read before their first write only through blocks with A = 0: keep them finite
   for (int t = threadIdx.x; t < 7 * nslots; t += 64 * kSweepWaves) ybuf[t] = (C)0;
   __syncthreads();
-  const int tb = wtask[s * kSweepWaves + wave], te = wtask[s * kSweepWaves + wave + 1];
-  int cur = 0;  // phase barriers passed
+  int seen = 0;      // a lower bound of min_w prog[w] (the phases only grow)
+  bool live = true;  // false once a wait has exceeded its bound
+  // wait until every row of a phase below p is finished; the acquire fence keeps the slot
+  // reads after the wait
+  auto wait_phase = [&](int p) {
+    if (p <= seen || !live) return;
+    for (int spins = 0;; ++spins) {
+      int m = nL;
+#pragma unroll
+      for (int w = 0; w < kSweepWaves; ++w)
+        m = min(m, __hip_atomic_load(&prog[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+      seen = __builtin_amdgcn_readfirstlane(m);
+      if (p <= seen) break;
+      if (spins == kSweepSpinLimit) {
+        live = false;
+        if (lane == 0) atomicOr(&flags[3], 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  };
   C acc[4] = {(C)0, (C)0, (C)0, (C)0};
   if (te > tb) {
     // c0 holds tasks [cb, cb + 64) and c1 the next chunk; consecutive chunks overlap by
@@ -582,19 +611,17 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
         }
         if (t < te) {
           const TaskMeta T = chunk_get(c0, t - cb);
-          while (cur < T.phase) {
-            lds_barrier();
-            ++cur;
-          }
+          wait_phase(T.phase);
           task_run<C, BWD, MB>(T, buf[k], ybuf_c, ybuf, yl, z, acc, r, c);
-          // The other wavefronts wait at the end of this phase for this one: when the next
-          // row of this wavefront finishes in a later phase (nothing more to write in this
-          // one), pass that barrier before the prefetch below and before any leading task
-          // of that row, so that the next phase's row waits for neither.
+          // Release: when the next task belongs to a row of a later phase, this wavefront's
+          // rows below that phase are finished; publish it (after the slot write and the
+          // slot reads have completed) before the prefetch below and before any leading
+          // task of that row, so that the rows waiting on it wait for neither.
           const int next_phase = t + 1 < te ? __builtin_amdgcn_readlane(c0.a.w, t + 1 - cb) : nL;
-          if (next_phase > cur) {
-            lds_barrier();
-            ++cur;
+          if (next_phase > mine) {
+            mine = next_phase;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            if (lane == 0) __hip_atomic_store(&prog[wave], mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
         // prefetch of task t + D - 1 into the set task t - 1 used (a fixed number of loads
@@ -604,10 +631,6 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
       }
     }
   }
-  while (cur < nL) {  // every wavefront passes the same number of barriers (one per phase)
-    lds_barrier();
-    ++cur;
-  }
 }
 
 template <typename S, int MB, int D>
@@ -615,7 +638,7 @@ static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, d
   using C = typename Value<S>::C;
   constexpr int NT = 64 * kSweepWaves;
   const size_t lds = (size_t)s->h.nslots * 7 * sizeof(C);
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (lds > 160 * 1024 - 64) return hipErrorInvalidConfiguration;  // 64 B for the progress phases
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_ilu_sweep<S, 0, MB, D>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -628,11 +651,11 @@ static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, d
   FSI_PROF_LAUNCH(s, "ilu_fwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->h.nslots));
+                                     z, s->flags, s->h.nslots));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->h.nslots));
+                                     z, s->flags, s->h.nslots));
   return hipGetLastError();
 }
 
