@@ -204,6 +204,14 @@ fsi_status fsi_newton_solve(fsi_solver *s, double *y, fsi_step_stats *st /* host
  * guesses of one step be compared at equal accuracy. */
 fsi_status fsi_set_newton_tol(fsi_solver *s, double rtol, double atol);
 
+/* Bound of the waits inside the factorization and the sweeps, in polls of a progress level
+ * (polls = -1 restores the default, about a second; 0 gives up at the first poll that finds
+ * the level not yet reached).  A wait past its bound stops waiting, so the kernel still
+ * ends, and the call reports error HIP: fsi_pc_setup, fsi_pc_apply, fsi_pc_tune,
+ * fsi_gmres and fsi_newton_solve.  For tests of that error path; the default is never reached by a
+ * correct schedule.  Drops captured graphs. */
+fsi_status fsi_set_wait_limit(fsi_solver *s, int32_t polls);
+
 /* ---- introspection (host copies; for tests and diagnostics) ---- */
 /* vkind[nverts]: 0 fluid, 1 interface, 2 wall; rowkind[n]: 0 element, 1 Dirichlet,
  * 2 kinematic, 3 dummy; interface triangles from Algorithm 1 as [n_iface][3]. */

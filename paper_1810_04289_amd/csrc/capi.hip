@@ -59,6 +59,12 @@ void clear_flags(fsi_solver* s) {
   hip_ok(s, hipMemsetAsync(s->flags, 0, 4 * sizeof(int32_t), s->stream), "memset flags");
 }
 
+// the sweeps' flag alone, before the calls that report it (so that an earlier call's
+// error does not carry over)
+void clear_sweep_flag(fsi_solver* s) {
+  hip_ok(s, hipMemsetAsync(s->flags + 3, 0, sizeof(int32_t), s->stream), "memset flag");
+}
+
 // the four device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound,
 // [3] sweep wait bound
 void read_flags(fsi_solver* s, int32_t out[4]) {
@@ -101,6 +107,7 @@ fsi_status pc_setup_impl(fsi_solver* s) {
     s->err = "pc_setup before jacobian";
     return FSI_ERR_ARG;
   }
+  s->pc_ready = false;  // until these factors are known good
   clear_flags(s);
   hip_ok(s, launch_pc_setup(s), "pc_setup");
   hip_ok(s, launch_fac_round(s), "factor rounding");
@@ -125,6 +132,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   const int64_t n = s->n;
   const int m = s->opts.gmres_restart, maxit = s->opts.gmres_maxit;
   fsi_lin_stats L{};
+  clear_sweep_flag(s);
   hip_ok(s, hipMemsetAsync(x, 0, n * sizeof(double), s->stream), "memset x");
   const double bnorm = norm2(s, b);
   L.rnorm0 = bnorm;
@@ -831,6 +839,7 @@ fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
   const double* a[2] = {v, z};
   return guard(s, [](fsi_solver* s, void* p) {
     const double** a = (const double**)p;
+    clear_sweep_flag(s);
     hip_ok(s, launch_pc_apply(s, a[0], (double*)a[1]), "pc_apply");
     if (read_flag(s, 3)) {
       s->err = "a Schwarz sweep waited on a row beyond its bound";
@@ -872,6 +881,7 @@ fsi_status fsi_pc_tune(fsi_solver* s, int32_t reps, int32_t* best_mb, double* us
     // probe input: the current residual vector (finite values); output to scratch
     double best_t = 0.0;
     int best = s->sweep_mb;
+    clear_sweep_flag(s);
     for (int c = 0; c < kSweepPlans; ++c) {
       const int mb = s->plans[c].mb;
       select_plan(s, mb);
@@ -890,6 +900,10 @@ fsi_status fsi_pc_tune(fsi_solver* s, int32_t reps, int32_t* best_mb, double* us
     if (a->best) *a->best = best;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (read_flag(s, 3)) {
+      s->err = "a Schwarz sweep waited on a row beyond its bound";
+      return FSI_ERR_HIP;
+    }
     return FSI_OK;
   }, &a);
 }
@@ -907,6 +921,18 @@ fsi_status fsi_gmres(fsi_solver* s, const double* rhs, double* x, fsi_lin_stats*
     sync(s);
     return rc;
   }, &a);
+}
+
+fsi_status fsi_set_wait_limit(fsi_solver* s, int32_t polls) {
+  if (!s) return FSI_ERR_ARG;
+  if (polls < -1) {
+    s->err = "wait limit below -1";
+    return FSI_ERR_ARG;
+  }
+  (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);  // captured launches hold the old limit
+  s->wait_limit = polls < 0 ? fsi::kWaitLimit : polls;
+  return FSI_OK;
 }
 
 fsi_status fsi_set_newton_tol(fsi_solver* s, double rtol, double atol) {

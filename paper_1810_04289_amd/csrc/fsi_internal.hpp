@@ -89,6 +89,9 @@ SweepTasks build_sweep_tasks(const HostSetup& h, bool bwd, const std::vector<int
 // One sweep schedule: task lists of both sweeps with tasks of at most mb blocks (the kernel
 // for mb fixes the prefetch depth).  kSweepPlanMB lists the candidates.
 constexpr int kSweepPlans = 4;
+// default bound of the factorization's and the sweeps' waits, in polls (about a second);
+// a correct schedule never comes near it
+constexpr int kWaitLimit = 1 << 23;
 constexpr int kSweepPlanMB[kSweepPlans] = {8, 16, 24, 32};
 struct SweepPlan {
   int mb = 0;
@@ -148,6 +151,8 @@ struct fsi_solver {
   // fw_row[fw_ptr[s*fac_nw + w] ..] (levels fw_lvl[..])
   int32_t* fgrp_lvl = nullptr;
   int fac_nw = 0;
+  // polls a factorization or sweep wait makes before it gives up and flags an error
+  int wait_limit = fsi::kWaitLimit;
   int32_t *fw_ptr = nullptr, *fw_row = nullptr, *fw_lvl = nullptr;
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;

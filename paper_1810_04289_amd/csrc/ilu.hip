@@ -68,9 +68,7 @@ __device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int vo
 }
 
 constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
-constexpr int kFacSpinLimit = 1 << 23;  // polls of a factorization wait before it gives up
-constexpr int kWaitVmcnt0 = 0x0F70;     // s_waitcnt operand: vmcnt(0), other counters free
-constexpr int kSweepSpinLimit = 1 << 23;  // polls of a sweep wait before it gives up
+constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt operand: vmcnt(0), other counters free
 
 struct FacDesc {  // one factorization group, uniform across the wavefront (see fsi_internal.hpp)
   int ublock, dk, moff, flags;
@@ -139,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int32_t* __restrict__ umap,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
-                                                   int maxrow) {
+                                                   int maxrow, int wait_limit) {
   extern __shared__ double lds[];
   constexpr int NW = NT / 64;
   const int s = blockIdx.x;
@@ -171,7 +169,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       for (int w = 0; w < NW; ++w) m = min(m, __hip_atomic_load(&prog[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
       seen = __builtin_amdgcn_readfirstlane(m);
       if (l < seen) break;
-      if (spins == kFacSpinLimit) {
+      if (spins == wait_limit) {
         live = false;
         if (lane == 0) atomicOr(&flags[2], 1);
         break;
@@ -347,7 +345,7 @@ hipError_t launch_pc_setup(fsi_solver* s) {
     FSI_PROF_LAUNCH(s, "ilu_factor",
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
                                        s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
-                                       s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk));
+                                       s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk, s->wait_limit));
     return hipSuccess;
   };
   constexpr int P = kFacDepth;
@@ -540,7 +538,8 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
                                                                const S* __restrict__ fac,
                                                                const double* __restrict__ v,
                                                                typename Value<S>::C* yl, double* __restrict__ z,
-                                                               int32_t* __restrict__ flags, int nslots) {
+                                                               int32_t* __restrict__ flags, int nslots,
+                                                               int wait_limit) {
   using C = typename Value<S>::C;
   extern __shared__ double lds_d[];
   C* lds = (C*)lds_d;
@@ -575,7 +574,7 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
         m = min(m, __hip_atomic_load(&prog[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
       seen = __builtin_amdgcn_readfirstlane(m);
       if (p <= seen) break;
-      if (spins == kSweepSpinLimit) {
+      if (spins == wait_limit) {
         live = false;
         if (lane == 0) atomicOr(&flags[3], 1);
         break;
@@ -651,11 +650,11 @@ static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, d
   FSI_PROF_LAUNCH(s, "ilu_fwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->flags, s->h.nslots));
+                                     z, s->flags, s->h.nslots, s->wait_limit));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->flags, s->h.nslots));
+                                     z, s->flags, s->h.nslots, s->wait_limit));
   return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ SYMBOLS = ["fsi_create", "fsi_destroy", "fsi_sizes", "fsi_last_error", "fsi_set_
            "fsi_impose_dirichlet", "fsi_residual", "fsi_jacobian", "fsi_jacobian_get", "fsi_jacobian_set",
            "fsi_spmv",
            "fsi_pc_setup", "fsi_pc_apply", "fsi_pc_tune", "fsi_pc_select", "fsi_set_graphs", "fsi_gmres", "fsi_newton_solve", "fsi_topology_get",
-           "fsi_pc_sizes", "fsi_pc_get", "fsi_prof_enable", "fsi_prof_get", "fsi_set_newton_tol"]
+           "fsi_pc_sizes", "fsi_pc_get", "fsi_prof_enable", "fsi_prof_get", "fsi_set_newton_tol",
+           "fsi_set_wait_limit"]
 # include/fsi_guess.h
 GUESS_SYMBOLS = ["fsi_mlp_create", "fsi_mlp_destroy", "fsi_mlp_last_error", "fsi_mlp_nparams", "fsi_mlp_set_params",
                  "fsi_mlp_get_params", "fsi_mlp_forward", "fsi_mlp_loss_grad", "fsi_mlp_train_step",
@@ -104,7 +105,7 @@ def load_library(path: str = LIB_PATH):
         "fsi_gmres": [vp, vp, vp, vp], "fsi_newton_solve": [vp, vp, vp],
         "fsi_topology_get": [vp, vp, vp, vp, vp], "fsi_pc_sizes": [vp, vp, vp, vp, vp],
         "fsi_pc_get": [vp] * 10, "fsi_prof_enable": [vp, i32], "fsi_prof_get": [vp, C.c_char_p, vp, vp],
-        "fsi_set_newton_tol": [vp, dbl, dbl], "fsi_pc_tune": [vp, i32, vp, vp], "fsi_pc_select": [vp, i32], "fsi_set_graphs": [vp, i32],
+        "fsi_set_newton_tol": [vp, dbl, dbl], "fsi_set_wait_limit": [vp, i32], "fsi_pc_tune": [vp, i32, vp, vp], "fsi_pc_select": [vp, i32], "fsi_set_graphs": [vp, i32],
         "fsi_mlp_create": [i32, i32, i32, i32, i64, vp, vp], "fsi_mlp_destroy": [vp],
         "fsi_mlp_set_params": [vp, vp], "fsi_mlp_get_params": [vp, vp, vp], "fsi_mlp_forward": [vp, vp, i64, vp],
         "fsi_mlp_loss_grad": [vp, vp, vp, i64, vp],
@@ -261,6 +262,10 @@ class Solver:
 
     def set_newton_tol(self, rtol, atol):
         self._chk(load_library().fsi_set_newton_tol(self.h, rtol, atol), "set_newton_tol")
+
+    def set_wait_limit(self, polls=-1):
+        """Bound of the factorization's and sweeps' waits in polls (-1: the default)."""
+        self._chk(load_library().fsi_set_wait_limit(self.h, int(polls)), "set_wait_limit")
 
     def newton_solve(self, y, check=True):
         st = StepStatsC()

@@ -693,3 +693,61 @@ def test_gmres_graph_replays_match_eager(fsi_mod):
         sols[on] = (yn.cpu().numpy(), st["newton_iters"], st["lin_hist"][:st["newton_iters"]])
     assert sols[True][1:] == sols[False][1:] and np.array_equal(sols[True][0], sols[False][0])
     s.set_graphs(False)
+
+
+def test_bounded_waits_report_errors(fsi_mod):
+    """The factorization's and the sweeps' waits on other wavefronts are bounded.  With the
+    bound forced to 0 polls from the host (give up at the first poll that finds a pivot row
+    or a read row unfinished), every kernel still ends and the calls report error HIP; a
+    failed setup leaves no usable preconditioner; with the default bound restored the same
+    preconditioner comes back bit for bit and GMRES converges."""
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    g = W.dirichlet_values(m, 30.0)
+    opts = dict(nsub=33, overlap=1, ilu_level=3, gmres_maxit=200)
+    P = Pair(fsi_mod, m, opts, np.zeros(m.n), g, mask=W.rigid_wall_mask(m))
+    y = P.o.impose_dirichlet(W.perturbed_state(m, np.zeros(m.n), seed=3))
+    s = P.g
+    yd = P.dev(y)
+    s.jacobian(yd)
+    s.pc_setup()
+    v = P.dev(np.random.default_rng(6).standard_normal(m.n))
+    z0 = s.vec()
+    s.pc_apply(v, z0)
+    HIP, ARG = 4, 1
+
+    s.set_wait_limit(0)
+    with pytest.raises(fsi_mod.FsiError) as e:
+        s.pc_apply(v, s.vec())
+    say(f"[bounded waits] sweeps: {e.value}")
+    assert e.value.code == HIP and "sweep" in str(e.value)
+    with pytest.raises(fsi_mod.FsiError) as e:
+        s.pc_setup()
+    say(f"[bounded waits] factorization: {e.value}")
+    assert e.value.code == HIP and "factorization" in str(e.value)
+    with pytest.raises(fsi_mod.FsiError) as e:  # no preconditioner after a failed setup
+        s.pc_apply(v, s.vec())
+    assert e.value.code == ARG
+
+    s.set_wait_limit(-1)
+    s.pc_setup()
+    z1 = s.vec()
+    s.pc_apply(v, z1)
+    assert torch.equal(z0, z1)
+
+    F = s.vec()
+    s.residual(yd, F)
+    rhs = -F
+    s.set_wait_limit(0)
+    with pytest.raises(fsi_mod.FsiError) as e:
+        s.gmres(rhs, s.vec())
+    assert e.value.code == HIP
+    with pytest.raises(fsi_mod.FsiError) as e:
+        s.pc_tune(reps=1)
+    assert e.value.code == HIP
+    s.set_wait_limit(-1)
+    s.pc_tune(reps=1)  # the flag of the failed calls does not carry over
+    st = s.gmres(rhs, s.vec())
+    say(f"[bounded waits] GMRES after restoring the bound: {st['iters']} iterations")
+    assert st["converged"]
+    with pytest.raises(fsi_mod.FsiError):
+        s.set_wait_limit(-2)
