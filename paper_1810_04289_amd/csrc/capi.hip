@@ -536,7 +536,7 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->fgrp = upload(s, grp);
     s->fgrp_lvl = upload(s, glvl);
     // rows round-robin over the factorization's wavefronts, in level order
-    s->fac_nw = fac_waves(s->max_rowblk);
+    s->fac_nw = fac_layout(s->max_rowblk).waves;
     if (s->fac_nw < 1) {
       s->err = "a local row is too long to stage in LDS for the factorization";
       return FSI_ERR_ARG;

@@ -187,7 +187,10 @@ hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
 bool select_plan(fsi_solver* s, int mb);
 // wavefronts of the factorization (each stages one row of up to max_rowblk blocks in LDS)
-int fac_waves(int max_rowblk);
+struct FacLayout {  // the factorization's wavefronts per subdomain and LDS slice (blocks)
+  int waves, slice;
+};
+FacLayout fac_layout(int max_rowblk);
 void drop_graphs(fsi_solver* s);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);

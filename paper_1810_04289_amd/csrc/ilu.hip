@@ -67,6 +67,13 @@ __device__ __forceinline__ double span_load_f64(__amdgpu_buffer_rsrc_t r, int vo
   return __hiloint2double((int)v.y, (int)v.x);
 }
 
+__device__ __forceinline__ void span_store_f64(__amdgpu_buffer_rsrc_t r, int voff, double x) {
+  u32x2_t v;
+  v.x = (unsigned)__double2loint(x);
+  v.y = (unsigned)__double2hiint(x);
+  __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, 0);
+}
+
 constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
 constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt operand: vmcnt(0), other counters free
 
@@ -105,7 +112,10 @@ __device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bo
 }
 
 // Factorization of one subdomain per workgroup, block IKJ order, one row at a time per
-// wavefront.  The row being factored is staged in the wavefront's LDS slice (maxrow blocks).
+// wavefront.  The row being factored is staged in the wavefront's LDS slice of `slice`
+// blocks; the blocks of a longer row past the slice stay in global memory and are updated
+// there (read-modify-write by the row's own wavefront, its stores completed before it
+// reads them again), so that a slice need not fit the longest row.
 // Its work is a list of groups built on the host: for each pivot k (ascending), U_k in
 // groups of up to 18 blocks (one group if U_k is empty).  The first group of a pivot forms
 // L_ik = A_ik D_k with lane e < 49 holding entry e, writes it back and reads it into every
@@ -137,7 +147,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int32_t* __restrict__ umap,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
-                                                   int maxrow, int wait_limit) {
+                                                   int slice, int wait_limit) {
   extern __shared__ double lds[];
   constexpr int NW = NT / 64;
   const int s = blockIdx.x;
@@ -150,8 +160,8 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   const bool qlane = lane < 7 * kFacHalf;
   const int voff_u = qlane ? 8 * (49 * qb + qc) : kOutside;
   const int voff_d = owner ? 8 * ent : kOutside;
-  double* row = lds + (size_t)wave * (maxrow * 49 + 56);
-  double* dsc = row + (size_t)maxrow * 49;  // D_k of the current pivot
+  double* row = lds + (size_t)wave * (slice * 49 + 56);
+  double* dsc = row + (size_t)slice * 49;  // D_k of the current pivot, then L_ik
   const int nL = nphase[s];
   const int wb = fw_ptr[s * NW + wave], we = fw_ptr[s * NW + wave + 1];
   __shared__ int prog[NW];  // progress levels of the wavefronts
@@ -184,7 +194,12 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     const int Li = __builtin_amdgcn_readfirstlane(fw_lvl[rw]);
     const int rb = __builtin_amdgcn_readfirstlane(lrowptr[i]);
     const int nbe = (__builtin_amdgcn_readfirstlane(lrowptr[i + 1]) - rb) * 49;
+    const int nbs = nbe < slice * 49 ? nbe : slice * 49;  // entries staged in LDS
+    const bool spill = nbe > nbs;                         // blocks past the slice in memory
     const size_t gb = (size_t)rb * 49;
+    double* grow = fac + gb;  // the row in memory
+    // the row's blocks past the slice are read and written through buffer instructions
+    const __amdgpu_buffer_rsrc_t rrow = span_rsrc(grow, 8 * nbe);
     const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
     const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
     // c0 holds groups [cb, cb + 64) (descriptors, and pivot levels in v0) and c1 / v1 the
@@ -197,17 +212,17 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     int4 c0 = chunk(0), c1 = chunk(kStride);
     int v0 = lchunk(0), v1 = lchunk(kStride);
     // stage the row: all loads of a round issued before its LDS writes
-    for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+    for (int e0 = 0; e0 < nbs; e0 += 64 * 8) {
       double tmp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
-        tmp[u] = fac[gb + (e < nbe ? e : nbe - 1)];
+        tmp[u] = grow[e < nbs ? e : nbs - 1];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
-        if (e < nbe) row[e] = tmp[u];
+        if (e < nbs) row[e] = tmp[u];
       }
     }
     wave_lds_sync();
@@ -218,15 +233,24 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
         if (owner) dsc[ent] = G.d;
         wave_lds_sync();
         double l = 0.0;
+        if (pik < slice) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
+          for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
+        } else {
+#pragma unroll
+          for (int m = 0; m < 7; ++m) l += span_load_f64(rrow, 8 * (pik * 49 + 7 * rr + m)) * dsc[7 * m + cc];
+        }
         wave_lds_sync();
-        if (owner) row[pik * 49 + ent] = l;
+        if (owner) {
+          dsc[ent] = l;
+          if (pik < slice) row[pik * 49 + ent] = l;
+          else span_store_f64(rrow, 8 * (pik * 49 + ent), l);
+        }
         wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < 7; ++r)
 #pragma unroll
-          for (int m = 0; m < 7; ++m) lrow[r][m] = row[pik * 49 + 7 * r + m];
+          for (int m = 0; m < 7; ++m) lrow[r][m] = dsc[7 * r + m];
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {  // A_ij -= L_ik U_kj, column qc
@@ -237,12 +261,19 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
 #pragma unroll
           for (int m = 0; m < 7; ++m) acc[r] += lrow[r][m] * G.u[h][m];
         }
-        if (qlane && G.pos[h] > 0) {
-          double* a = row + (G.pos[h] - 1) * 49 + qc;
+        const int p = G.pos[h] - 1;
+        if (qlane && p >= 0 && p < slice) {
+          double* a = row + p * 49 + qc;
 #pragma unroll
           for (int r = 0; r < 7; ++r) a[7 * r] -= acc[r];
+        } else if (qlane && p >= slice) {
+          const int o = 8 * (p * 49 + qc);
+#pragma unroll
+          for (int r = 0; r < 7; ++r) span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[r]);
         }
       }
+      // a later group may read back what this one stored past the slice
+      if (spill) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       wave_lds_sync();
     };
     if (ng > 0) {
@@ -273,8 +304,8 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       }
     }
     // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
-    const int pd = (__builtin_amdgcn_readfirstlane(ldiag[i]) - rb) * 49;
-    double M = row[pd + ent];
+    const int pdb = __builtin_amdgcn_readfirstlane(ldiag[i]) - rb;  // block position of A_ii
+    double M = pdb < slice ? row[pdb * 49 + ent] : span_load_f64(rrow, 8 * (pdb * 49 + ent));
     if (owner) udiag[49 * (size_t)i + ent] = M;
     double Iv = (rr == cc) ? 1.0 : 0.0;
     bool bad = false;
@@ -298,19 +329,23 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     }
     if (bad && lane == 0) atomicOr(&flags[1], 1);
     wave_lds_sync();
-    if (owner) row[pd + ent] = Iv;
+    if (owner) {
+      if (pdb < slice) row[pdb * 49 + ent] = Iv;
+      else span_store_f64(rrow, 8 * (pdb * 49 + ent), Iv);
+    }
     wave_lds_sync();
-    for (int e0 = 0; e0 < nbe; e0 += 64 * 8) {
+    // write back the staged part; blocks past the slice are already in place
+    for (int e0 = 0; e0 < nbs; e0 += 64 * 8) {
       double tmp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
-        tmp[u] = row[e < nbe ? e : nbe - 1];
+        tmp[u] = row[e < nbs ? e : nbs - 1];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
-        if (e < nbe) fac[gb + e] = tmp[u];
+        if (e < nbs) grow[e] = tmp[u];
       }
     }
     // release: once the write-back has completed, raise the progress level to the next
@@ -324,9 +359,18 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   }
 }
 
-int fac_waves(int max_rowblk) {
-  const size_t per_wave = ((size_t)max_rowblk * 49 + 56) * sizeof(double);
-  return (int)std::min<size_t>(4, (160 * 1024 - 64) / per_wave);  // 64 B for the progress levels
+// LDS of the factorization: per wavefront a slice of `slice` staged blocks plus D_k, and 64 B
+// for the progress levels.  As many wavefronts (up to four) as slices for the longest row
+// fit; but when four slices of at least 90% of the longest row fit, four wavefronts with
+// such slices, the few longer rows keeping their tails in memory.
+FacLayout fac_layout(int max_rowblk) {
+  const size_t cap = 160 * 1024 - 64;
+  auto per_wave = [](size_t blocks) { return (blocks * 49 + 56) * sizeof(double); };
+  const int full = (int)std::min<size_t>(4, cap / per_wave((size_t)max_rowblk));
+  if (full >= 4) return FacLayout{4, max_rowblk};
+  const int s4 = (int)((cap / 4 / sizeof(double) - 56) / 49);
+  if (10 * s4 >= 9 * max_rowblk) return FacLayout{4, s4};
+  return FacLayout{full, max_rowblk};
 }
 
 hipError_t launch_pc_setup(fsi_solver* s) {
@@ -335,9 +379,10 @@ hipError_t launch_pc_setup(fsi_solver* s) {
                      s->fac);
   // up to four row-staging wavefronts per workgroup, as many as the longest row allows (the
   // rows were dealt to that many wavefronts at create)
-  const size_t per_wave = ((size_t)s->max_rowblk * 49 + 56) * sizeof(double);
+  const FacLayout fl = fac_layout(s->max_rowblk);
   const int waves = s->fac_nw;
-  if (waves < 1 || waves != fac_waves(s->max_rowblk)) return hipErrorInvalidConfiguration;
+  if (waves < 1 || waves != fl.waves || fl.slice < 1) return hipErrorInvalidConfiguration;
+  const size_t per_wave = ((size_t)fl.slice * 49 + 56) * sizeof(double);
   const size_t lds = per_wave * waves;
   auto go = [&](auto kern, int nt) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -345,7 +390,7 @@ hipError_t launch_pc_setup(fsi_solver* s) {
     FSI_PROF_LAUNCH(s, "ilu_factor",
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
                                        s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
-                                       s->ldiag, s->fac, s->udiag, s->flags, s->max_rowblk, s->wait_limit));
+                                       s->ldiag, s->fac, s->udiag, s->flags, fl.slice, s->wait_limit));
     return hipSuccess;
   };
   constexpr int P = kFacDepth;
