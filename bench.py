@@ -217,7 +217,8 @@ def main():
 
     kernels = {}
     for name in ("ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid", "jac_gather",
-                 "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate"):
+                 "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate", "vupdate_mdot",
+                 "vupdate_sqnorm"):
         ms, cnt = s.prof_get(name)
         kernels[name] = {"total_ms": round(ms, 3), "count": cnt, "avg_us": round(1e3 * ms / cnt, 2) if cnt else None}
     s.prof_enable(False)

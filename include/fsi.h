@@ -181,7 +181,7 @@ fsi_status fsi_pc_select(fsi_solver *s, int32_t mb);
 
 /* GMRES's inner step as captured graphs (on != 0): the preconditioner, the SpMV, both
  * Gram-Schmidt passes and the norm of each Arnoldi step j are captured into one graph on
- * first use and replayed afterwards, one launch instead of eleven.  Results are identical
+ * first use and replayed afterwards, one launch instead of nine.  Results are identical
  * to the eager path (same kernels, same order).  Graphs are dropped when the sweep
  * schedule changes or graphs are switched off; while kernel profiling (fsi_prof_enable) is
  * on, GMRES runs eagerly.  In graph mode the preconditioner's time in fsi_step_stats is

@@ -178,10 +178,8 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
     hipError_t e = launch_pc_apply(s, s->Vb + (size_t)j * n, s->z);
     if (e == hipSuccess) e = launch_spmv(s, s->z, s->w);
     if (e == hipSuccess) e = launch_mdot(s, s->Vb, j + 1, s->w, n, hA);
-    if (e == hipSuccess) e = launch_vupdate(s, s->Vb, j + 1, hA, s->w, n);
-    if (e == hipSuccess) e = launch_mdot(s, s->Vb, j + 1, s->w, n, hB);
-    if (e == hipSuccess) e = launch_vupdate(s, s->Vb, j + 1, hB, s->w, n);
-    if (e == hipSuccess) e = launch_dot_partial(s, s->w, s->w, n, hn2);
+    if (e == hipSuccess) e = launch_vupdate_mdot(s, s->Vb, j + 1, hA, s->w, n, hB);
+    if (e == hipSuccess) e = launch_vupdate_sqnorm(s, s->Vb, j + 1, hB, s->w, n, hn2);
     return e;
   };
   auto arnoldi_step = [&](int j) {
@@ -189,10 +187,8 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
       timed_pc(s->Vb + (size_t)j * n, s->z);
       hip_ok(s, launch_spmv(s, s->z, s->w), "spmv");
       hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hA), "mdot");
-      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hA, s->w, n), "vupdate");
-      hip_ok(s, launch_mdot(s, s->Vb, j + 1, s->w, n, hB), "mdot");
-      hip_ok(s, launch_vupdate(s, s->Vb, j + 1, hB, s->w, n), "vupdate");
-      hip_ok(s, launch_dot_partial(s, s->w, s->w, n, hn2), "norm");
+      hip_ok(s, launch_vupdate_mdot(s, s->Vb, j + 1, hA, s->w, n, hB), "vupdate+mdot");
+      hip_ok(s, launch_vupdate_sqnorm(s, s->Vb, j + 1, hB, s->w, n, hn2), "vupdate+norm");
       return;
     }
     if (!s->arnoldi[j]) {

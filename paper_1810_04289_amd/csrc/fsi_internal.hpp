@@ -195,6 +195,12 @@ void drop_graphs(fsi_solver* s);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);
 hipError_t launch_vupdate(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n);
+// the second Gram-Schmidt pass's coefficients into hout, fused with the first pass's update
+hipError_t launch_vupdate_mdot(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n,
+                               double* hout);
+// the second pass's update fused with |w|^2 into out
+hipError_t launch_vupdate_sqnorm(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n,
+                                 double* out);
 hipError_t launch_vcombine(fsi_solver* s, const double* Vb, int nv, const double* y, double* out, int64_t n);
 hipError_t launch_axpby(fsi_solver* s, double a, const double* x, double b, const double* y, double* out, int64_t n);
 hipError_t launch_scale(fsi_solver* s, double a, const double* x, double* out, int64_t n);

@@ -97,6 +97,70 @@ __global__ void __launch_bounds__(256) k_vupdate(const double* __restrict__ Vb, 
   w[k] = acc;
 }
 
+// The two halves of a Gram-Schmidt step that meet at w, fused so that the basis is read
+// once: w -= sum_i h[i] V_i, then partial[b*32 + i] = block b's share of V_i . w (the new
+// w).  Each element's basis values stay in registers between the two (140 VGPRs, three
+// wavefronts per SIMD), so the grid is kFusedBlocks blocks, all resident at once on 256 CUs;
+// the fixed grid and lane order keep the sums deterministic.  nv <= 32.
+constexpr int kFusedBlocks = 768;
+__global__ void __launch_bounds__(256) k_vupdate_mdot(const double* __restrict__ Vb, int nv,
+                                                      const double* __restrict__ h, double* __restrict__ w,
+                                                      int64_t n, double* __restrict__ partial) {
+  __shared__ double sw[4][32];
+  double acc[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) acc[i] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = i < nv ? Vb[(size_t)i * n + k] : 0.0;
+    double wk = w[k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < nv) wk -= h[i] * v[i];
+    w[k] = wk;
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < nv) acc[i] += v[i] * wk;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    if (i < nv) {
+      double x = wave_sum(acc[i]);
+      if (lane == 0) sw[wave][i] = x;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv)
+    partial[(size_t)blockIdx.x * 32 + threadIdx.x] =
+        (sw[0][threadIdx.x] + sw[1][threadIdx.x]) + (sw[2][threadIdx.x] + sw[3][threadIdx.x]);
+}
+
+// w -= sum_i h[i] V_i, then partial[b] = block b's share of w . w, in the element order and
+// block reduction of k_dot_partial (bit for bit a k_vupdate and a k_dot_partial).  nv <= 32.
+__global__ void __launch_bounds__(256) k_vupdate_sqnorm(const double* __restrict__ Vb, int nv,
+                                                        const double* __restrict__ h, double* __restrict__ w,
+                                                        int64_t n, double* __restrict__ partial) {
+  __shared__ double sw[4];
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double v[32];  // all of the element's basis values requested before the first is used
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = i < nv ? Vb[(size_t)i * n + k] : 0.0;
+    double wk = w[k];
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < nv) wk -= h[i] * v[i];
+    w[k] = wk;
+    acc += wk * wk;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
+}
+
 // out = sum_i y[i] V_i (accumulate = 1 adds to out)
 __global__ void __launch_bounds__(256) k_vcombine(const double* __restrict__ Vb, int nv, const double* __restrict__ y,
                                                   double* __restrict__ out, int64_t n, int accumulate) {
@@ -142,6 +206,32 @@ hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w,
                                        Vb + (size_t)i0 * n, c, n, w, s->partial));
     hipLaunchKernelGGL(k_reduce_partials, dim3(c), dim3(64), 0, s->stream, s->partial, kRedBlocks, 32, h + i0);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_vupdate_mdot(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n,
+                               double* hout) {
+  if (nv > 32) {
+    hipError_t e = launch_vupdate(s, Vb, nv, h, w, n);
+    return e == hipSuccess ? launch_mdot(s, Vb, nv, w, n, hout) : e;
+  }
+  FSI_PROF_LAUNCH(s, "vupdate_mdot",
+                  hipLaunchKernelGGL(k_vupdate_mdot, dim3(kFusedBlocks), dim3(256), 0, s->stream, Vb, nv, h, w, n,
+                                     s->partial));
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(64), 0, s->stream, s->partial, kFusedBlocks, 32, hout);
+  return hipGetLastError();
+}
+
+hipError_t launch_vupdate_sqnorm(fsi_solver* s, const double* Vb, int nv, const double* h, double* w, int64_t n,
+                                 double* out) {
+  if (nv > 32) {
+    hipError_t e = launch_vupdate(s, Vb, nv, h, w, n);
+    return e == hipSuccess ? launch_dot_partial(s, w, w, n, out) : e;
+  }
+  FSI_PROF_LAUNCH(s, "vupdate_sqnorm",
+                  hipLaunchKernelGGL(k_vupdate_sqnorm, dim3(kRedBlocks), dim3(256), 0, s->stream, Vb, nv, h, w, n,
+                                     s->partial));
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s->stream, s->partial, kRedBlocks, 1, out);
   return hipGetLastError();
 }
 
