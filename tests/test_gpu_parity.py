@@ -424,6 +424,31 @@ def test_gmres_fixed_cycle_parity(fsi_mod, rigid):
     assert err <= (1e-10 if rigid else 1e-4)
 
 
+def test_gmres_long_restart_parity(fsi_mod):
+    """A restart length above 32: the Gram-Schmidt kernels take the basis in chunks of 32
+    vectors (the fused update-and-dot kernels fall back to separate launches there).  40
+    iterations in one cycle, rigid wall, ILU(0): on this small tube the residual reaches
+    rounding level by then, and the iterates agree with the oracle's."""
+    m, y0, g = tube_problem()
+    opts = dict(nsub=4, overlap=1, ilu_level=0, gmres_rtol=0.0, gmres_maxit=40, gmres_restart=40)
+    P = Pair(fsi_mod, m, opts, y0, g, mask=W.rigid_wall_mask(m))
+    y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
+    P.o.jacobian(y)
+    P.g.jacobian_set(P.o.jacobian_get()[2])
+    P.g.pc_setup()
+    P.o.pc_setup()
+    b = -P.o.residual(y)
+    x = P.g.vec()
+    stg = P.g.gmres(P.dev(b), x)
+    xr, sto = P.o.gmres(b)
+    err = np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)
+    say(f"[gmres40 restart 40] its {stg['iters']} vs {sto['iters']}, x rel {err:.3e}, "
+        f"res {stg['rnorm_true']:.9e} vs {sto['rnorm_true']:.9e} (r0 {sto['rnorm0']:.3e})")
+    assert stg["iters"] == sto["iters"] == 40
+    assert abs(stg["rnorm_true"] - sto["rnorm_true"]) <= 1e-8 * sto["rnorm0"]
+    assert err <= 1e-8
+
+
 def test_newton_step_parity(fsi_mod):
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=3)
