@@ -241,7 +241,7 @@ def main():
         "gmres_iters": float(np.mean([x["linear_iters"] for x in stats])),
     }
     phases = {k: float(np.mean([x[k] for x in stats])) for k in
-              ("t_funceval", "t_jaceval", "t_pcsetup", "t_pcapply", "t_kspsolve")}
+              ("t_funceval", "t_jaceval", "t_pcsetup", "t_pcapply", "t_kspsolve", "t_kspsetup")}
     schwarz_cfg = dict(nsub=args.nsub, ilu_level=args.ilu, overlap=args.overlap, ordering=args.ordering,
                        sweep_mb=tune["best_blocks_per_task"] if tune else None)
     out = {

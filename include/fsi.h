@@ -106,7 +106,10 @@ typedef struct {
 } fsi_lin_stats;
 
 #define FSI_MAX_NEWTON 64
-/* Per-step statistics; the six phase timers carry the paper's event names (Table 7). */
+/* Per-step statistics; the six phase timers carry the paper's event names (Table 7).
+ * t_kspsolve includes t_pcapply and t_kspsetup (each GMRES solve's set-up before its first
+ * Arnoldi step: the initial vector, the norm of the right-hand side; the workspace itself
+ * is allocated once, at create). */
 typedef struct {
   int32_t newton_iters, linear_iters, line_search_cuts, converged;
   double fnorm0, fnorm;

@@ -128,7 +128,11 @@ fsi_status pc_setup_impl(fsi_solver* s) {
 // Right-preconditioned restarted GMRES (§3 eq. (13)); classical Gram-Schmidt applied twice,
 // Givens rotations rho = hypot(a,b), c = a/rho, s = b/rho; happy breakdown when
 // h_{j+1,j} <= 1e-14 ||h||; stop when |g_{j+1}| <= rtol ||b||.
-fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* st, double* t_pc) {
+// t_pc (may be null) accumulates the preconditioner's time, t_setup (may be null) the
+// solve's set-up before its first Arnoldi step (the paper's KSPSetUp).
+fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* st, double* t_pc,
+                      double* t_setup) {
+  const double ts0 = now();
   const int64_t n = s->n;
   const int m = s->opts.gmres_restart, maxit = s->opts.gmres_maxit;
   fsi_lin_stats L{};
@@ -139,6 +143,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   if (bnorm == 0.0) {
     L.converged = 1;
     if (st) *st = L;
+    if (t_setup) *t_setup += now() - ts0;
     return FSI_OK;
   }
   const double target = s->opts.gmres_rtol * bnorm;
@@ -153,6 +158,7 @@ fsi_status gmres_impl(fsi_solver* s, const double* b, double* x, fsi_lin_stats* 
   hipEvent_t e0, e1;
   hip_ok(s, hipEventCreate(&e0), "event");
   hip_ok(s, hipEventCreate(&e1), "event");
+  if (t_setup) *t_setup += now() - ts0;
   // the preconditioner is bracketed by events; its time is read after the iteration's
   // own synchronization (no extra host wait between the sweeps and the SpMV)
   bool pc_timed = false;
@@ -344,7 +350,7 @@ fsi_status newton_impl(fsi_solver* s, double* y, fsi_step_stats* st) {
     fsi_lin_stats ls{};
     t0 = now();
     double tpc = 0.0;
-    const fsi_status lrc = gmres_impl(s, s->rhs, s->dy, &ls, &tpc);
+    const fsi_status lrc = gmres_impl(s, s->rhs, s->dy, &ls, &tpc, &S.t_kspsetup);
     S.t_kspsolve += now() - t0;
     if (lrc != FSI_OK) {
       status = lrc;
@@ -913,7 +919,7 @@ fsi_status fsi_gmres(fsi_solver* s, const double* rhs, double* x, fsi_lin_stats*
   } a{rhs, x, st};
   return guard(s, [](fsi_solver* s, void* p) {
     A* a = (A*)p;
-    fsi_status rc = gmres_impl(s, a->b, a->x, a->st, nullptr);
+    fsi_status rc = gmres_impl(s, a->b, a->x, a->st, nullptr, nullptr);
     sync(s);
     return rc;
   }, &a);
