@@ -12,7 +12,7 @@ setups, GMRES iterations, line searches) through the library's C ABI.  Before th
 the flow is started by two rigid-wall steps from rest (untimed setup of the initial
 state).  Inputs (mesh, step Dirichlet data) are resident in HBM before timing starts.
 
-Prints one JSON line.  With --gpus N > 1 it exits: this build runs on one GPU.
+Prints one JSON line.  With --gpus N > 1 it exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -138,8 +138,8 @@ def main():
                          "(reference dispatch for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of the Schwarz subdomains is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library does not "
+              "shard the Schwarz subdomains over several GPUs.", file=sys.stderr)
         sys.exit(2)
 
     import torch
