@@ -271,10 +271,38 @@ def main():
                  "frac": round(spmv_gbs / HBM_PEAK, 4) if spmv_gbs else None},
         "kernels": kernels,
     }
+    if args.precision != 0:
+        out["error_vs_fp64"] = error_vs_fp64(s, fsi, mesh, ph, opts, G, rigid, dt, nsteps, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap, args.ordering)
     print(json.dumps(out), flush=True)
     s.close()
+
+
+def error_vs_fp64(s, fsi, mesh, ph, opts, G, rigid, dt, nsteps, dev):
+    """Outside the timed steps: every step of the run taken from the same state (the FP64
+    path's) by the rounded-preconditioner solver s and by an FP64 solver; the relative
+    2-norm difference of their results per step, and the Newton tolerance both meet."""
+    import torch
+    s64 = fsi.Solver(mesh, ph, dict(opts, precision=0))
+    y_old = torch.zeros(s.n, dtype=torch.float64, device=dev)
+    ya, yb = torch.empty_like(y_old), torch.empty_like(y_old)
+    rel = []
+    for k in range(nsteps):
+        mask = rigid if k < 2 else None
+        for solver, y in ((s64, ya), (s, yb)):
+            solver.set_step((k + 1) * dt, dt, y_old, G[k], None, mask)
+            y.copy_(y_old)
+            st, rc = solver.newton_solve(y, check=False)
+            if rc != 0:
+                raise RuntimeError(f"comparison step {k} failed with status {rc}")
+        rel.append(float(torch.linalg.vector_norm(yb - ya) / torch.linalg.vector_norm(ya)))
+        y_old.copy_(ya)
+        log(f"[bench] step {k}: rounded-preconditioner state vs FP64 rel {rel[-1]:.3e}")
+    s64.close()
+    return {"per_step_rel_2norm": [float(f"{r:.3e}") for r in rel], "max": float(f"{max(rel):.3e}"),
+            "newton_rtol": opts["newton_rtol"],
+            "note": "each step from the FP64 path's previous state; both solves meet the same Newton tolerance"}
 
 
 if __name__ == "__main__":
