@@ -39,24 +39,28 @@ def log(*a):
 
 
 def stored_traffic(kernel: str, precision: int, config: dict):
-    """HBM bytes per launch measured with rocprofv3 counters, if the profile on record was
-    taken with the current sweep source, the same sweep precision and the same Schwarz
-    configuration (subdomains, fill level, overlap, ordering, sweep schedule); None
-    otherwise."""
+    """HBM bytes per launch measured with rocprofv3 counters, from a profile on record
+    (profiles/ilu_sweep_traffic_tree3*.json, one per sweep schedule) taken with the current
+    sweep source, the same sweep precision and the same Schwarz configuration (subdomains,
+    fill level, overlap, ordering, sweep schedule); None if there is none."""
+    import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3.json")
-    try:
-        rec = json.load(open(path))
-    except (OSError, ValueError):
-        return None
     src = open(os.path.join(ROOT, "paper_1810_04289_amd", "csrc", "ilu.hip"), "rb").read()
-    if rec.get("ilu_hip_sha256") != hashlib.sha256(src).hexdigest() or rec.get("precision", 0) != precision:
-        return None
-    rec_cfg = rec.get("config", {"nsub": 256, "ilu_level": 3, "overlap": 1, "ordering": 0})
-    if any(rec_cfg.get(k) != config.get(k) for k in ("nsub", "ilu_level", "overlap", "ordering", "sweep_mb")):
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    sha = hashlib.sha256(src).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "ilu_sweep_traffic_tree3*.json"))):
+        try:
+            rec = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        if rec.get("ilu_hip_sha256") != sha or rec.get("precision", 0) != precision:
+            continue
+        rec_cfg = rec.get("config", {"nsub": 256, "ilu_level": 3, "overlap": 1, "ordering": 0})
+        if any(rec_cfg.get(k) != config.get(k) for k in ("nsub", "ilu_level", "overlap", "ordering", "sweep_mb")):
+            continue
+        k = rec.get("kernels", {}).get(kernel)
+        if k is not None:
+            return k.get("hbm_bytes_per_launch")
+    return None
 
 
 ORDERING = {0: "RCM", 1: "1WD"}
@@ -132,6 +136,9 @@ def main():
                     help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the row-length rule's sweep schedule")
+    ap.add_argument("--sweep-mb", type=int, default=0,
+                    help="use this sweep schedule (blocks per task) instead of tuning, e.g. to take "
+                         "counters on the schedule a tuned run chose")
     ap.add_argument("--graphs", action="store_true", help="GMRES Arnoldi steps as captured graphs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB three times "
@@ -184,7 +191,11 @@ def main():
         log(f"[bench] warmup step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
 
     tune = None
-    if not args.no_tune:  # sweep schedule timed on the last step's factors, outside the timed steps
+    if args.sweep_mb:
+        s.pc_select(args.sweep_mb)
+        tune = {"best_blocks_per_task": args.sweep_mb, "selected": True}
+        log(f"[bench] sweep schedule selected: {args.sweep_mb} blocks per task")
+    elif not args.no_tune:  # sweep schedule timed on the last step's factors, outside the timed steps
         best, us = s.pc_tune(3)
         tune = {"best_blocks_per_task": best, "us_per_apply": {str(k): round(v, 1) for k, v in us.items()}}
         log(f"[bench] sweep schedule: {tune}")
