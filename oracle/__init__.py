@@ -91,7 +91,7 @@ def lib():
             "fsio_create": [vp, vp, vp, vp], "fsio_destroy": [vp], "fsio_sizes": [vp, vp, vp],
             "fsio_set_step": [vp, dbl, dbl, vp, vp, vp, vp], "fsio_impose_dirichlet": [vp, vp],
             "fsio_residual": [vp, vp, vp], "fsio_residual_complex": [vp, vp, vp, vp, vp],
-            "fsio_jacobian": [vp, vp], "fsio_jacobian_get": [vp, vp, vp, vp],
+            "fsio_jacobian": [vp, vp], "fsio_jacobian_get": [vp, vp, vp, vp], "fsio_jacobian_set": [vp, vp],
             "fsio_spmv": [vp, vp, vp], "fsio_pc_setup": [vp], "fsio_pc_apply": [vp, vp, vp],
             "fsio_gmres": [vp, vp, vp, vp], "fsio_newton_solve": [vp, vp, vp],
             "fsio_topology_get": [vp, vp, vp, vp, vp], "fsio_pc_sizes": [vp, vp, vp, vp, vp],
@@ -203,6 +203,11 @@ class Oracle:
         vals = np.zeros((self.nnzb, 7, 7))
         self._chk(lib().fsio_jacobian_get(self.h, _p(rp), _p(ci), _p(vals)), "jacobian_get")
         return rp, ci, vals
+
+    def jacobian_set(self, vals):
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        assert vals.size == self.nnzb * 49
+        self._chk(lib().fsio_jacobian_set(self.h, _p(vals)), "jacobian_set")
 
     def spmv(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

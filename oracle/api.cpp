@@ -122,6 +122,13 @@ int fsio_jacobian_get(const fsio_solver* s, int32_t* rowptr, int32_t* colind, do
   return FSIO_OK;
 }
 
+int fsio_jacobian_set(fsio_solver* s, const double* vals) {
+  if (!s || !vals) return FSIO_ERR_ARG;
+  std::copy(vals, vals + s->J.vals.size(), s->J.vals.begin());
+  s->jac_ready = true;
+  return FSIO_OK;
+}
+
 int fsio_spmv(fsio_solver* s, const double* x, double* y) {
   if (!s || !x || !y || !s->jac_ready) return FSIO_ERR_ARG;
   spmv(*s, x, y);

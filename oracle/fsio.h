@@ -81,6 +81,8 @@ int fsio_residual_complex(fsio_solver *s, const double *y_re, const double *y_im
                           double *F_im);
 int fsio_jacobian(fsio_solver *s, const double *y);
 int fsio_jacobian_get(const fsio_solver *s, int32_t *rowptr, int32_t *colind, double *vals);
+/* replace the Jacobian's values (same pattern as fsio_jacobian_get reports) */
+int fsio_jacobian_set(fsio_solver *s, const double *vals);
 int fsio_spmv(fsio_solver *s, const double *x, double *y);
 int fsio_pc_setup(fsio_solver *s);
 int fsio_pc_apply(fsio_solver *s, const double *v, double *z);
