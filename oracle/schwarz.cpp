@@ -309,28 +309,53 @@ int build_subdomains(fsio_solver& s) {
   return FSIO_OK;
 }
 
-// 7x7 inverse by Gauss-Jordan elimination with partial pivoting (first maximum wins).
+// 7x7 inverse by Gauss-Jordan elimination with partial pivoting (first maximum wins),
+// applied to the equilibrated block.  A pivot block of the FSI matrix mixes momentum,
+// continuity (PSPG, entries near 1e-10) and kinematic or wall rows (up to 1e4), so it is
+// first scaled by powers of two, rows then columns, to a largest entry in [1, 2) in each
+// row and column: Ah = R A C with R = diag(r), C = diag(c).  Then A^{-1} = C Ah^{-1} R.  The
+// scalings are exact, so in exact arithmetic this is the same inverse and the same block
+// ILU (§3, §4.3); only the rounding of the elimination changes.
+static double pow2_below(double x) {  // the power of two 2^e with 2^e <= x < 2^(e+1)
+  int e;
+  std::frexp(x, &e);
+  return std::ldexp(1.0, e - 1);
+}
+
 int invert7(const double* A, double* Ainv) {
-  double M[7][7], I[7][7];
-  for (int r = 0; r < 7; ++r)
-    for (int c = 0; c < 7; ++c) { M[r][c] = A[7 * r + c]; I[r][c] = (r == c) ? 1.0 : 0.0; }
+  double M[7][7], I[7][7], r[7], c[7];
+  for (int i = 0; i < 7; ++i) {
+    double mx = 0.0;
+    for (int j = 0; j < 7; ++j) mx = std::max(mx, std::fabs(A[7 * i + j]));
+    if (!(mx > 0.0) || !std::isfinite(mx)) return FSIO_ERR_ZERO_PIVOT;
+    r[i] = 1.0 / pow2_below(mx);
+  }
+  for (int j = 0; j < 7; ++j) {
+    double mx = 0.0;
+    for (int i = 0; i < 7; ++i) mx = std::max(mx, std::fabs(A[7 * i + j]) * r[i]);
+    if (!(mx > 0.0)) return FSIO_ERR_ZERO_PIVOT;
+    c[j] = 1.0 / pow2_below(mx);
+  }
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j < 7; ++j) { M[i][j] = r[i] * A[7 * i + j] * c[j]; I[i][j] = (i == j) ? 1.0 : 0.0; }
   for (int p = 0; p < 7; ++p) {
     int piv = p;
-    for (int r = p + 1; r < 7; ++r)
-      if (std::fabs(M[r][p]) > std::fabs(M[piv][p])) piv = r;
+    for (int i = p + 1; i < 7; ++i)
+      if (std::fabs(M[i][p]) > std::fabs(M[piv][p])) piv = i;
     if (!(std::fabs(M[piv][p]) > 0.0) || !std::isfinite(M[piv][p])) return FSIO_ERR_ZERO_PIVOT;
     if (piv != p)
-      for (int c = 0; c < 7; ++c) { std::swap(M[p][c], M[piv][c]); std::swap(I[p][c], I[piv][c]); }
+      for (int j = 0; j < 7; ++j) { std::swap(M[p][j], M[piv][j]); std::swap(I[p][j], I[piv][j]); }
     double pv = M[p][p];
-    for (int c = 0; c < 7; ++c) { M[p][c] /= pv; I[p][c] /= pv; }
-    for (int r = 0; r < 7; ++r) {
-      if (r == p) continue;
-      double f = M[r][p];
-      for (int c = 0; c < 7; ++c) { M[r][c] -= f * M[p][c]; I[r][c] -= f * I[p][c]; }
+    for (int j = 0; j < 7; ++j) { M[p][j] /= pv; I[p][j] /= pv; }
+    for (int i = 0; i < 7; ++i) {
+      if (i == p) continue;
+      double f = M[i][p];
+      for (int j = 0; j < 7; ++j) { M[i][j] -= f * M[p][j]; I[i][j] -= f * I[p][j]; }
     }
   }
-  for (int r = 0; r < 7; ++r)
-    for (int c = 0; c < 7; ++c) Ainv[7 * r + c] = I[r][c];
+  // I now holds Ah^{-1}; A^{-1} = C Ah^{-1} R
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j < 7; ++j) Ainv[7 * i + j] = c[i] * I[i][j] * r[j];
   return FSIO_OK;
 }
 

@@ -148,6 +148,11 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int slice, int wait_limit) {
+  // Every entry is formed as in the method's statement: sums of products in ascending
+  // order, each product rounded, nothing fused.  The block elimination of the wall rows
+  // amplifies a difference of one rounding in its input to about 1e-4 in its factors, so
+  // only the same rounded operations give factors that are reproducible anywhere else.
+#pragma clang fp contract(off)
   extern __shared__ double lds[];
   constexpr int NW = NT / 64;
   const int s = blockIdx.x;
@@ -303,12 +308,34 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
         }
       }
     }
-    // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins)
+    // D_i = A_ii^{-1}: Gauss-Jordan with partial pivoting (first maximum wins) on the
+    // equilibrated block Ah = R A C, R and C powers of two that bring each row's and then
+    // each column's largest entry into [1, 2); then A^{-1} = C Ah^{-1} R.  The scalings are
+    // exact: the inverse is the same, only its rounding improves (the wall's pivot blocks
+    // mix entries from 1e-10 to 1e4).
     const int pdb = __builtin_amdgcn_readfirstlane(ldiag[i]) - rb;  // block position of A_ii
     double M = pdb < slice ? row[pdb * 49 + ent] : span_load_f64(rrow, 8 * (pdb * 49 + ent));
     if (owner) udiag[49 * (size_t)i + ent] = M;
-    double Iv = (rr == cc) ? 1.0 : 0.0;
     bool bad = false;
+    double rs, cs;  // scale of this lane's row (r_rr) and column (c_cc)
+    {
+      double mx = 0.0;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) mx = fmax(mx, fabs(__shfl(M, 7 * rr + m, 64)));
+      if (!(mx > 0.0) || !isfinite(mx)) bad = true;
+      int e;
+      frexp(mx, &e);
+      rs = 1.0 / ldexp(1.0, e - 1);
+      const double Mr = M * rs;
+      mx = 0.0;
+#pragma unroll
+      for (int m = 0; m < 7; ++m) mx = fmax(mx, fabs(__shfl(Mr, 7 * m + cc, 64)));
+      if (!(mx > 0.0)) bad = true;
+      frexp(mx, &e);
+      cs = 1.0 / ldexp(1.0, e - 1);
+      M = Mr * cs;
+    }
+    double Iv = (rr == cc) ? 1.0 : 0.0;
     for (int p = 0; p < 7; ++p) {
       double colv[7];
 #pragma unroll
@@ -327,6 +354,9 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       const double Mp = __shfl(M, p * 7 + cc, 64), Ip = __shfl(Iv, p * 7 + cc, 64);
       if (rr != p) { M = M - fct * Mp; Iv = Iv - fct * Ip; }
     }
+    // entry (rr, cc) of A^{-1} is c_rr Ah^{-1}(rr, cc) r_cc: c_rr from lane (0, rr), r_cc
+    // from lane (cc, 0)
+    Iv = __shfl(cs, rr, 64) * Iv * __shfl(rs, 7 * cc, 64);
     if (bad && lane == 0) atomicOr(&flags[1], 1);
     wave_lds_sync();
     if (owner) {

@@ -5,9 +5,11 @@ multiply-adds):
   residual           ||F_gpu - F_ref||_2 / ||F_ref||_2            <= 1e-10
   Jacobian           max_i ||J_gpu(i,:) - J_ref(i,:)||_inf / ||J_ref(i,:)||_inf <= 1e-12
   integer setup      exact (topology, block pattern, partition, overlap, RCM, fill)
-  ILU factors        rounding-level agreement on a well-conditioned matrix; on the FSI
-                     matrix (ill-conditioned elimination) backward error LU - A relative
-                     to |L||U| on the pattern
+  ILU factors        identical, bit for bit, from the same matrix (both sides form every
+                     entry with the same rounded operations in the same order: the
+                     elimination of the wall rows moves its factors by about 1e-4 for a
+                     change of one rounding in its input, so nothing weaker is
+                     reproducible); backward error LU - A relative to |L||U| <= 1e-12
   B^{-1} v, SpMV     normwise relative
   fixed GMRES cycle  normwise relative
   Newton step        within the Newton tolerance
@@ -215,8 +217,8 @@ def factor_errors(a, b):
 
 @pytest.mark.parametrize("level", [0, 2])
 def test_ilu_factor_parity_on_the_same_matrix(fsi_mod, level):
-    """The GPU factors the oracle's own Jacobian (wall frozen, so the elimination is well
-    conditioned): the factors and B^{-1} v agree to rounding."""
+    """The GPU factors the oracle's own Jacobian (wall frozen): the factors are identical
+    and B^{-1} v agrees to rounding."""
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=level)
     P = Pair(fsi_mod, m, opts, y0, g, mask=W.rigid_wall_mask(m))
@@ -235,7 +237,7 @@ def test_ilu_factor_parity_on_the_same_matrix(fsi_mod, level):
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     say(f"[ilu{level} same J, rigid wall] factor row-rel L {e['L']:.2e} D {e['D']:.2e} U {e['U']:.2e}, "
         f"B^-1 v rel {ez:.3e}")
-    assert max(e.values()) <= 1e-10
+    assert np.array_equal(a["factors"], b["factors"]) and np.array_equal(a["udiag"], b["udiag"])
     assert ez <= 1e-11
 
 
@@ -281,13 +283,18 @@ def lu_backward_error(pc, s, A_rows, verts_map=None):
     return worst
 
 
-def test_ilu_backward_error_on_the_fsi_matrix(fsi_mod):
-    """FSI rows: the elimination of the thin-wall elasticity is ill conditioned, so GPU and
-    oracle factors of the same matrix differ in their digits; what is unique is that both
-    satisfy LU = A on the pattern up to rounding relative to |L||U| (backward error), and
-    that the GPU sweeps solve L U z = v to rounding."""
+@pytest.mark.parametrize("level", [0, 2])
+def test_ilu_factor_parity_on_the_fsi_matrix(fsi_mod, level):
+    """FSI rows with the compliant wall, one subdomain.  Both sides factor the same matrix:
+    the factors must be identical; both factorizations satisfy LU = A on the pattern to
+    1e-12 relative to |L||U| (measured 7.8e-15 for ILU(0) and 4.1e-14 for ILU(2); the
+    pivot blocks are inverted after equilibration -- without it this reads 1.4e-11 and
+    2.4e-10); the GPU sweeps solve L U z = v with a residual below 1e-11 relative to
+    |L||U||z| (measured 4.8e-14 and 2.0e-12: the stored D_i carries the equilibrated
+    pivot's conditioning, up to 4e4 here); and B^{-1} v agrees to 1e-11 (measured 5.7e-14
+    and 2.2e-12)."""
     m, y0, g = tube_problem()
-    opts = dict(nsub=1, overlap=0, ilu_level=2)
+    opts = dict(nsub=1, overlap=0, ilu_level=level)
     P = Pair(fsi_mod, m, opts, y0, g)
     y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
     P.o.jacobian(y)
@@ -308,24 +315,24 @@ def test_ilu_backward_error_on_the_fsi_matrix(fsi_mod):
     eg = lu_backward_error(a, 0, A_rows)
     eo = lu_backward_error(b, 0, A_rows)
     e = factor_errors(a, b)
-    # block LU's backward error carries the inverted pivots' conditioning: L_ik = A_ik D_k
-    # with D_k = inv(U_kk) accurate to cond(U_kk) eps, hence the bound below
     kappa = float(max(np.linalg.cond(u) for u in b["udiag"]))
-    bound = 64 * np.finfo(float).eps * kappa
-    say(f"[ilu2 fsi same J] backward error gpu {eg:.2e} oracle {eo:.2e} (bound {bound:.1e}, "
-        f"max cond(U_kk) {kappa:.1e}); forward factor diff L {e['L']:.1e} D {e['D']:.1e} U {e['U']:.1e}")
-    assert eg <= bound and eo <= bound
+    say(f"[ilu{level} fsi same J] factors identical {np.array_equal(a['factors'], b['factors'])}, "
+        f"row-rel L {e['L']:.1e} D {e['D']:.1e} U {e['U']:.1e}; backward error gpu {eg:.2e} oracle {eo:.2e} "
+        f"(max cond(U_kk) {kappa:.1e})")
+    assert np.array_equal(a["factors"], b["factors"]) and np.array_equal(a["udiag"], b["udiag"])
+    assert eg <= 1e-12 and eo <= 1e-12
     # sweeps: z solves (LU) z = v in the local (RCM) order, to rounding
     v = np.random.default_rng(4).standard_normal(m.n)
     z = P.g.vec()
     P.g.pc_apply(P.dev(v), z)
+    zr = P.o.pc_apply(v)
+    ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     zl = z.cpu().numpy()[idx]
     vl = v[idx]
     # rebuild L and U of the GPU factors and check the residual of the two triangular solves
     lrp = a["lrowptr"][0:len(verts) + 1]
     f = a["factors"]
     ud = a["udiag"]
-    res = 0.0
     # (L U) z = v  <=>  U z = L^{-1} v;  evaluate r = L (U z) - v blockwise with magnitudes
     Uz = np.zeros((len(verts), 7))
     aUz = np.zeros((len(verts), 7))
@@ -346,11 +353,9 @@ def test_ilu_backward_error_on_the_fsi_matrix(fsi_mod):
                 r[i] += f[k] @ Uz[j]
                 ar[i] += np.abs(f[k]) @ aUz[j]
     res = float((np.abs(r.ravel() - vl) / np.maximum(ar.ravel(), 1e-300)).max())
-    # the backward sweep applies the stored inverse D_i = inv(U_ii), accurate to
-    # cond(U_ii) eps, so the residual carries the same conditioning factor
-    kg = float(max(np.linalg.cond(u) for u in a["udiag"]))
-    say(f"  sweep residual |LUz - v| / (|L||U||z|) = {res:.2e} (bound {64 * np.finfo(float).eps * kg:.1e})")
-    assert res <= 64 * np.finfo(float).eps * kg
+    say(f"  sweep residual |LUz - v| / (|L||U||z|) = {res:.2e}; B^-1 v rel {ez:.2e}")
+    assert res <= 1e-11
+    assert ez <= 1e-11
 
 
 def test_pc_apply_parity_own_jacobians_stable_case(fsi_mod):
@@ -374,36 +379,43 @@ def test_pc_apply_parity_own_jacobians_stable_case(fsi_mod):
 
 
 def test_pc_apply_parity_own_jacobians_fsi(fsi_mod):
-    """Full FSI rows: the block ILU of the thin-wall elasticity is unstable (factor growth
-    of order 1e5-1e7), which amplifies the 1e-13 difference between the two Jacobians; the
-    bound below is that growth times the Jacobian tolerance."""
+    """Full FSI rows, each side assembling its own Jacobian.  The two Jacobians agree to
+    rounding, but the block elimination of the wall rows amplifies a change of one rounding
+    in its input to about 1e-4 in its factors (measured: 1.3e-4 here, 1.1e-5 on B^{-1} v), so
+    the oracle is given the GPU's Jacobian: from the same matrix the factors must be
+    identical and B^{-1} v agree to 1e-11 (measured 8.1e-14), and the two Jacobians agree
+    to 1e-12 row-relative."""
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=2)
     P = Pair(fsi_mod, m, opts, y0, g)
     y = P.o.impose_dirichlet(W.perturbed_state(m, y0, seed=7))
     P.g.jacobian(P.dev(y))
     P.o.jacobian(y)
+    rp, ci, Vg = P.g.jacobian_get()
+    _, _, Vr = P.o.jacobian_get()
+    ej = jac_rowrel(rp, ci, Vg, Vr, m.nverts)
+    P.o.jacobian_set(Vg)
     P.g.pc_setup()
     P.o.pc_setup()
-    b = P.o.pc_get()
-    _, _, Vr = P.o.jacobian_get()
-    growth = float(np.abs(b["factors"]).max() / np.abs(Vr).max())
+    a, b = P.g.pc_get(), P.o.pc_get()
     v = np.random.default_rng(2).standard_normal(m.n)
     z = P.g.vec()
     P.g.pc_apply(P.dev(v), z)
     zr = P.o.pc_apply(v)
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
-    say(f"[pc own J, fsi] growth {growth:.1e}, B^-1 v rel {ez:.3e}")
-    # measured amplification of rounding by this elimination is about 1e-5 even on an
-    # identical matrix (see the backward-error test); the bound leaves a factor 10
-    assert ez <= 1e-4
+    say(f"[pc own J, fsi] J row-rel {ej:.1e}, factors identical {np.array_equal(a['factors'], b['factors'])}, "
+        f"B^-1 v rel {ez:.3e}")
+    assert ej <= 1e-12
+    assert np.array_equal(a["factors"], b["factors"])
+    assert ez <= 1e-11
 
 
 @pytest.mark.parametrize("rigid", [True, False])
 def test_gmres_fixed_cycle_parity(fsi_mod, rigid):
-    """Twelve GMRES iterations (rtol 0) on the same operator.  With the wall frozen the
-    preconditioner is well conditioned and the iterates agree to rounding; with FSI rows
-    the residual histories still agree, the iterates to the preconditioner's amplification."""
+    """Twelve GMRES iterations (rtol 0) on the same operator.  The factors are identical on
+    both sides; the iterates differ by the rounding of the sweeps, the SpMV and the
+    Gram-Schmidt sums: 1e-10 with the wall frozen, 1e-9 with the compliant wall (measured
+    7.0e-11: its preconditioned operator is far worse conditioned)."""
     m, y0, g = tube_problem()
     opts = dict(nsub=4, overlap=1, ilu_level=2, gmres_rtol=0.0, gmres_maxit=12, gmres_restart=30)
     P = Pair(fsi_mod, m, opts, y0, g, mask=W.rigid_wall_mask(m) if rigid else None)
@@ -421,7 +433,7 @@ def test_gmres_fixed_cycle_parity(fsi_mod, rigid):
         f"res {stg['rnorm_true']:.9e} vs {sto['rnorm_true']:.9e}")
     assert stg["iters"] == sto["iters"] == 12
     assert abs(stg["rnorm_true"] - sto["rnorm_true"]) <= 1e-8 * sto["rnorm0"]
-    assert err <= (1e-10 if rigid else 1e-4)
+    assert err <= (1e-10 if rigid else 1e-9)
 
 
 def test_gmres_long_restart_parity(fsi_mod):
@@ -587,10 +599,8 @@ def test_full_size_residual_parity(tree, fsi_mod):
             errs.append(np.abs(acc - Aij).max(1))
             scales = np.maximum(scales, aacc.max(1))
         worst = max(worst, float((np.max(errs, axis=0) / scales).max()))
-    kappa = float(max(np.linalg.cond(u) for u in ud))
-    bound = 64 * np.finfo(float).eps * kappa
-    say(f"  full-size LU=A on pattern (subdomain {s}), relative to |L||U|: {worst:.3e} (bound {bound:.1e})")
-    assert worst <= bound
+    say(f"  full-size LU=A on pattern (subdomain {s}), relative to |L||U|: {worst:.3e}")
+    assert worst <= 1e-12
 
 
 @pytest.mark.parametrize("rigid,ordering", [(True, 0), (False, 0), (False, 1)])
@@ -615,13 +625,14 @@ def test_tree_schwarz_parity_bench_like(fsi_mod, rigid, ordering):
     zr = P.o.pc_apply(v)
     ez = np.linalg.norm(z.cpu().numpy() - zr) / np.linalg.norm(zr)
     b = P.o.pc_get()
-    kappa = float(max(np.linalg.cond(u) for u in b["udiag"]))
-    if ordering:
-        a = P.g.pc_get(factors=False)
-        for k in ("sub_ptr", "sub_verts", "blk_ptr", "lrowptr", "lcolind"):
-            assert np.array_equal(a[k], b[k]), k
-    say(f"[tree1 rigid={rigid} ordering={ordering}] V={m.nverts} B^-1 v rel {ez:.3e}, max cond(U_kk) {kappa:.1e}")
-    assert ez <= (1e-10 if rigid else max(1e-8, 64 * np.finfo(float).eps * kappa))
+    a = P.g.pc_get()
+    for k in ("sub_ptr", "sub_verts", "blk_ptr", "lrowptr", "lcolind"):
+        assert np.array_equal(a[k], b[k]), k
+    same = np.array_equal(a["factors"], b["factors"])
+    say(f"[tree1 rigid={rigid} ordering={ordering}] V={m.nverts} factors identical {same}, B^-1 v rel {ez:.3e}")
+    # measured on the compliant wall: 3.1e-15 (RCM) and 8.2e-16 (1WD)
+    assert same
+    assert ez <= (1e-10 if rigid else 1e-11)
     rhs = -P.o.residual(y)
     x = P.g.vec()
     st = P.g.gmres(P.dev(rhs), x)
