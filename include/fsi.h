@@ -170,6 +170,20 @@ fsi_status fsi_pc_setup(fsi_solver *s);
 /* z = B^{-1} v = sum_i (R_i^0)^T (L_i U_i)^{-1} R_i^delta v. */
 fsi_status fsi_pc_apply(fsi_solver *s, const double *v /* dev, n */, double *z /* dev, n */);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): fsi_pc_apply with the sweeps' work
+ * values and error flags in a static per-GPU scratch array of the library instead of the
+ * solver's buffers.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); like fsi_pc_apply it waits for its stream work and reads one error
+ * flag back.  The scratch holds 32 MiB of sweep values: 7 values per local (overlapped)
+ * subdomain row, FP64 with FSI_PREC_FP64 and FP32 otherwise, i.e. up to 599,186 local
+ * rows in FP64.  Larger solvers get ERR_ARG with a message that says so.  Every call on
+ * one GPU, from any solver, uses that GPU's one copy of the array and leaves its contents
+ * there: calls that overlap on one GPU (on different streams or host threads) race.
+ * Results equal fsi_pc_apply's bit for bit (same kernels, same order).  Errors as
+ * fsi_pc_apply, and HIP if the scratch's address could not be taken at fsi_create. */
+fsi_status fsi_pc_apply_noalloc(fsi_solver *s, const double *v /* dev, n */, double *z /* dev, n */);
+
 /* Schedule of the Schwarz sweeps.  Every subdomain's forward and backward sweep runs in one
  * launch per sweep, one workgroup per subdomain; rows are cut into tasks of at most mb
  * blocks, and the kernel for mb prefetches a matching number of tasks.  The candidates are

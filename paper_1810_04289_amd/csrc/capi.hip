@@ -5,13 +5,53 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 
 #include "fsi_internal.hpp"
 
 using namespace fsi;
 
+// Scratch of the allocation-free Schwarz application (fsi_pc_apply_noalloc): a file-scope
+// device array, one copy on every GPU the library runs on, held until the process ends.
+// Its first 256 bytes hold the sweeps' four error flags, the rest the forward sweep's
+// values (7 per local row, FP64 or FP32), up to kScratchYBytes.  Host code reaches a
+// GPU's copy only through the address hipGetSymbolAddress returns on that GPU; the
+// array's name in host code is a stand-in, not a device address.
+constexpr size_t kScratchFlagBytes = 256;
+constexpr size_t kScratchYBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kScratchFlagBytes + kScratchYBytes];
+
 namespace {
+
+struct ScratchAddr {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+constexpr int kMaxDevices = 64;
+ScratchAddr g_scratch[kMaxDevices];
+
+// With the solver's device current: the address of that device's scratch, looked up once
+// per device.
+void scratch_attach(fsi_solver* s) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    s->scratch_err = e != hipSuccess ? e : hipErrorInvalidDevice;
+    return;
+  }
+  ScratchAddr& a = g_scratch[dev];
+  std::call_once(a.once, [&a] { a.err = hipGetSymbolAddress(&a.ptr, HIP_SYMBOL(scratch)); });
+  s->scratch_err = a.err;
+  s->scratch = a.err == hipSuccess ? (char*)a.ptr : nullptr;
+}
+
+// clears n int32 (a kernel, not a memset, so that the call can be captured in a graph)
+__global__ void k_zero_i32(int32_t* p, int n) {
+  const int i = threadIdx.x;
+  if (i < n) p[i] = 0;
+}
 
 struct Fail {
   fsi_status st;
@@ -592,6 +632,7 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   hip_ok(s, hipMemset(s->flags, 0, 4 * sizeof(int32_t)), "memset");
   hip_ok(s, hipMemset(s->hdev, 0, 4 * (kMaxRestart + 8) * sizeof(double)), "memset");
   hip_ok(s, hipDeviceSynchronize(), "sync");
+  scratch_attach(s);
   return FSI_OK;
 }
 
@@ -844,6 +885,42 @@ fsi_status fsi_pc_apply(fsi_solver* s, const double* v, double* z) {
     clear_sweep_flag(s);
     hip_ok(s, launch_pc_apply(s, a[0], (double*)a[1]), "pc_apply");
     if (read_flag(s, 3)) {
+      s->err = "a Schwarz sweep waited on a row beyond its bound";
+      return FSI_ERR_HIP;
+    }
+    return FSI_OK;
+  }, a);
+}
+
+fsi_status fsi_pc_apply_noalloc(fsi_solver* s, const double* v, double* z) {
+  if (!s || !v || !z || !s->pc_ready) return FSI_ERR_ARG;
+  const double* a[2] = {v, z};
+  return guard(s, [](fsi_solver* s, void* p) {
+    const double** a = (const double**)p;
+    if (!s->scratch) {
+      s->err = std::string("no scratch address on this device: ") + hipGetErrorString(s->scratch_err);
+      return FSI_ERR_HIP;
+    }
+    const size_t need = pc_apply_ws_bytes(s);
+    if (need > kScratchYBytes) {
+      s->err = "fsi_pc_apply_noalloc: the sweeps need " + std::to_string(need) + " bytes of scratch (" +
+               std::to_string(s->R) + " local rows), above its " + std::to_string(kScratchYBytes) + " bytes";
+      return FSI_ERR_ARG;
+    }
+    int32_t* fl = (int32_t*)s->scratch;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s->stream, fl, 4);
+    hip_ok(s, hipGetLastError(), "clear scratch flags");
+    const bool prof = s->prof;  // kernel timing would create events: off for this call
+    s->prof = false;
+    const hipError_t e = launch_pc_apply_ws(s, a[0], (double*)a[1], s->scratch + kScratchFlagBytes, fl);
+    s->prof = prof;
+    hip_ok(s, e, "pc_apply_noalloc");
+    hip_ok(s, hipMemcpyAsync(&s->pinned[200], fl + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+           "flag readback");
+    sync(s);
+    int32_t f;
+    std::memcpy(&f, &s->pinned[200], sizeof f);
+    if (f) {
       s->err = "a Schwarz sweep waited on a row beyond its bound";
       return FSI_ERR_HIP;
     }

@@ -163,6 +163,10 @@ struct fsi_solver {
   double *F = nullptr, *Ft = nullptr, *yt = nullptr, *dy = nullptr, *rhs = nullptr;
   int32_t* flags = nullptr;      // [0] inverted, [1] zero pivot
   double* pinned = nullptr;      // host-pinned readback buffer (256 doubles)
+  // this solver's device's copy of the allocation-free entry point's scratch (capi.hip),
+  // or null with scratch_err set if its address could not be taken
+  char* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
   std::vector<void*> allocs;
 
   bool prof = false;
@@ -183,6 +187,10 @@ hipError_t launch_impose(fsi_solver* s, double* y);
 hipError_t launch_spmv(fsi_solver* s, const double* x, double* y);
 hipError_t launch_pc_setup(fsi_solver* s);
 hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z);
+// the same with the sweeps' work values (pc_apply_ws_bytes of them) and error flags (four
+// int32) in caller-given device memory
+hipError_t launch_pc_apply_ws(fsi_solver* s, const double* v, double* z, void* yl_ws, int32_t* flags_ws);
+size_t pc_apply_ws_bytes(const fsi_solver* s);
 hipError_t launch_fac_round(fsi_solver* s);
 int sweep_task_blocks(int longest_part);
 bool select_plan(fsi_solver* s, int mb);

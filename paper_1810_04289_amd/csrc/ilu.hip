@@ -707,8 +707,11 @@ __global__ void __launch_bounds__(64 * kSweepWaves) k_ilu_sweep(const int32_t* _
   }
 }
 
+// yl_ws: the forward sweep's results, 7 values of the arithmetic type per local row (every
+// one written before it is read); flags_ws: the four error flags (the sweeps raise [3])
 template <typename S, int MB, int D>
-static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, double* z) {
+static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, double* z, void* yl_ws,
+                                int32_t* flags_ws) {
   using C = typename Value<S>::C;
   constexpr int NT = 64 * kSweepWaves;
   const size_t lds = (size_t)s->h.nslots * 7 * sizeof(C);
@@ -721,25 +724,26 @@ static hipError_t launch_sweeps(fsi_solver* s, const S* facs, const double* v, d
                               (int)lds);
     if (e != hipSuccess) return e;
   }
-  C* yl = (C*)s->ylocal;
+  C* yl = (C*)yl_ws;
   FSI_PROF_LAUNCH(s, "ilu_fwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 0, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->fwd_nphase, s->fwd_wtask, s->fwd_task, s->fwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->flags, s->h.nslots, s->wait_limit));
+                                     z, flags_ws, s->h.nslots, s->wait_limit));
   FSI_PROF_LAUNCH(s, "ilu_bwd",
                   hipLaunchKernelGGL((k_ilu_sweep<S, 1, MB, D>), dim3(s->h.ns), dim3(NT), lds, s->stream,
                                      s->bwd_nphase, s->bwd_wtask, s->bwd_task, s->bwd_task_aux, s->lslot, facs, v, yl,
-                                     z, s->flags, s->h.nslots, s->wait_limit));
+                                     z, flags_ws, s->h.nslots, s->wait_limit));
   return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t launch_sweeps_mb(fsi_solver* s, const S* facs, const double* v, double* z) {
+static hipError_t launch_sweeps_mb(fsi_solver* s, const S* facs, const double* v, double* z, void* yl_ws,
+                                   int32_t* flags_ws) {
   switch (s->sweep_mb) {  // the candidates of kSweepPlanMB, each with its prefetch depth
-    case 8: return launch_sweeps<S, 8, 6>(s, facs, v, z);
-    case 16: return launch_sweeps<S, 16, 4>(s, facs, v, z);
-    case 24: return launch_sweeps<S, 24, 3>(s, facs, v, z);
-    case 32: return launch_sweeps<S, 32, 2>(s, facs, v, z);
+    case 8: return launch_sweeps<S, 8, 6>(s, facs, v, z, yl_ws, flags_ws);
+    case 16: return launch_sweeps<S, 16, 4>(s, facs, v, z, yl_ws, flags_ws);
+    case 24: return launch_sweeps<S, 24, 3>(s, facs, v, z, yl_ws, flags_ws);
+    case 32: return launch_sweeps<S, 32, 2>(s, facs, v, z, yl_ws, flags_ws);
     default: return hipErrorInvalidValue;
   }
 }
@@ -749,13 +753,21 @@ static hipError_t launch_sweeps_mb(fsi_solver* s, const S* facs, const double* v
 // prefetched blocks within the register file.
 int sweep_task_blocks(int longest_part) { return longest_part <= 16 ? 16 : 24; }
 
-hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
+hipError_t launch_pc_apply_ws(fsi_solver* s, const double* v, double* z, void* yl_ws, int32_t* flags_ws) {
   switch (s->opts.precision) {
-    case FSI_PREC_FP64: return launch_sweeps_mb<double>(s, s->fac, v, z);
-    case FSI_PREC_FP32: return launch_sweeps_mb<float>(s, (const float*)s->facs, v, z);
-    case FSI_PREC_BF16: return launch_sweeps_mb<bf16_t>(s, (const bf16_t*)s->facs, v, z);
+    case FSI_PREC_FP64: return launch_sweeps_mb<double>(s, s->fac, v, z, yl_ws, flags_ws);
+    case FSI_PREC_FP32: return launch_sweeps_mb<float>(s, (const float*)s->facs, v, z, yl_ws, flags_ws);
+    case FSI_PREC_BF16: return launch_sweeps_mb<bf16_t>(s, (const bf16_t*)s->facs, v, z, yl_ws, flags_ws);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_pc_apply(fsi_solver* s, const double* v, double* z) {
+  return launch_pc_apply_ws(s, v, z, s->ylocal, s->flags);
+}
+
+size_t pc_apply_ws_bytes(const fsi_solver* s) {
+  return (size_t)s->R * 7 * (s->opts.precision == FSI_PREC_FP64 ? sizeof(double) : sizeof(float));
 }
 
 // Sweep copy of the factors: FP64 rounded to nearest FP32, or to nearest-even BF16.

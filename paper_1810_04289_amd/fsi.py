@@ -21,7 +21,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_MESH", 3: "ERR_OOM", 4: "ERR_HIP", 5: "
 SYMBOLS = ["fsi_create", "fsi_destroy", "fsi_sizes", "fsi_last_error", "fsi_set_step",
            "fsi_impose_dirichlet", "fsi_residual", "fsi_jacobian", "fsi_jacobian_get", "fsi_jacobian_set",
            "fsi_spmv",
-           "fsi_pc_setup", "fsi_pc_apply", "fsi_pc_tune", "fsi_pc_select", "fsi_set_graphs", "fsi_gmres", "fsi_newton_solve", "fsi_topology_get",
+           "fsi_pc_setup", "fsi_pc_apply", "fsi_pc_apply_noalloc", "fsi_pc_tune", "fsi_pc_select", "fsi_set_graphs", "fsi_gmres", "fsi_newton_solve", "fsi_topology_get",
            "fsi_pc_sizes", "fsi_pc_get", "fsi_prof_enable", "fsi_prof_get", "fsi_set_newton_tol",
            "fsi_set_wait_limit"]
 # include/fsi_guess.h
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "fsi_residual": [vp, vp, vp], "fsi_jacobian": [vp, vp], "fsi_jacobian_get": [vp, vp, vp, vp],
         "fsi_jacobian_set": [vp, vp],
         "fsi_spmv": [vp, vp, vp], "fsi_pc_setup": [vp], "fsi_pc_apply": [vp, vp, vp],
+        "fsi_pc_apply_noalloc": [vp, vp, vp],
         "fsi_gmres": [vp, vp, vp, vp], "fsi_newton_solve": [vp, vp, vp],
         "fsi_topology_get": [vp, vp, vp, vp, vp], "fsi_pc_sizes": [vp, vp, vp, vp, vp],
         "fsi_pc_get": [vp] * 10, "fsi_prof_enable": [vp, i32], "fsi_prof_get": [vp, C.c_char_p, vp, vp],
@@ -192,6 +193,9 @@ class Solver:
         if rc:
             raise FsiError(rc, f"{what}: {load_library().fsi_last_error(self.h).decode()}")
 
+    def last_error(self) -> str:
+        return load_library().fsi_last_error(self.h).decode()
+
     def vec(self, a=None):
         t = self.torch
         if a is None:
@@ -239,6 +243,13 @@ class Solver:
 
     def pc_apply(self, v, z):
         self._chk(load_library().fsi_pc_apply(self.h, _dptr(v), _dptr(z)), "pc_apply")
+
+    def pc_apply_noalloc(self, v, z, check=True):
+        """fsi_pc_apply_noalloc: the same operator, scratch in the library's static per-GPU array."""
+        rc = load_library().fsi_pc_apply_noalloc(self.h, _dptr(v), _dptr(z))
+        if check:
+            self._chk(rc, "pc_apply_noalloc")
+        return rc
 
     SWEEP_MB = (8, 16, 24, 32)
 
