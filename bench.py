@@ -66,22 +66,15 @@ def stored_traffic(kernel: str, precision: int, config: dict):
 ORDERING = {0: "RCM", 1: "1WD"}
 
 
-def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1,
-                 ordering: int = 0) -> dict:
-    """The oracle (1 host core) timed on a bounded sample and scaled to the workload.
-
-    Sample: the depth-1 tree (about 26k vertices, cut into subdomains of the workload's
-    size), one call each of FuncEval, JacEval and PCSetUp and 8 GMRES iterations; the
-    per-call times are combined with the GPU run's per-step call counts and scaled by the
-    vertex ratio (every phase is linear in the mesh size at fixed subdomain size).
-    """
+def oracle_phase_times(m, nsub: int, ilu_level: int, overlap: int, ordering: int) -> dict:
+    """Seconds of one oracle call of FuncEval, JacEval and PCSetUp on mesh m, and of one GMRES
+    iteration averaged over a whole restart cycle of 30 (the Gram-Schmidt cost grows with
+    the basis index), at a perturbed rest state of the first step."""
     import oracle as O
     O.build()
-    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
     ph = W.physics_config1()
-    ns = max(1, round(nsub_work * m.nverts / V_work))
-    o = O.Oracle(m, ph, dict(nsub=ns, overlap=overlap, ilu_level=ilu_level, ordering=ordering, gmres_rtol=0.0,
-                             gmres_maxit=8))
+    o = O.Oracle(m, ph, dict(nsub=nsub, overlap=overlap, ilu_level=ilu_level, ordering=ordering, gmres_rtol=0.0,
+                             gmres_maxit=30, gmres_restart=30))
     g = W.dirichlet_values(m, 30.0)
     y0 = W.perturbed_state(m, np.zeros(m.n), seed=1)
     o.set_step(1e-3, 1e-3, np.zeros(m.n), g)
@@ -98,26 +91,106 @@ def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, over
     t0 = time.perf_counter()
     _, st = o.gmres(-F)
     t_it = (time.perf_counter() - t0) / max(st["iters"], 1)
-    per_step = (counts["funceval"] * t_fe + counts["jaceval"] * t_je + counts["pcsetup"] * t_ps +
-                counts["gmres_iters"] * t_it)
+    return {"funceval": t_fe, "jaceval": t_je, "pcsetup": t_ps, "gmres_iter": t_it, "gmres_iters_timed": st["iters"]}
+
+
+def per_step(t: dict, counts: dict) -> float:
+    return (counts["funceval"] * t["funceval"] + counts["jaceval"] * t["jaceval"] + counts["pcsetup"] * t["pcsetup"] +
+            counts["gmres_iters"] * t["gmres_iter"])
+
+
+def cpu_baseline(counts: dict, ilu_level: int, V_work: int, nsub_work: int, overlap: int = 1,
+                 ordering: int = 0, small_mesh=None) -> dict:
+    """The oracle (1 host core) timed on a bounded sample and scaled to the workload.
+
+    Sample: the depth-1 tree (about 26k vertices, cut into subdomains of the workload's
+    size), one call each of FuncEval, JacEval and PCSetUp and a 30-iteration GMRES cycle;
+    the per-call times are combined with the GPU run's per-step call counts and scaled by
+    the vertex ratio (every phase is linear in the mesh size at fixed subdomain size).
+    `bench.py --validate-cpu-baseline` checks that scaling against the oracle's phases
+    timed on the workload's own mesh.
+    """
+    if small_mesh is not None:  # a workload small enough to time whole
+        t = oracle_phase_times(small_mesh, nsub_work, ilu_level, overlap, ordering)
+        return {"value": per_step(t, counts), "unit": "s/step", "cores": 1, "kind": "oracle",
+                "sample": (f"oracle phases on the workload's own mesh ({small_mesh.nverts} vertices): FuncEval "
+                           f"{t['funceval']:.4f}s, JacEval {t['jaceval']:.4f}s, PCSetUp {t['pcsetup']:.4f}s, GMRES iter "
+                           f"{t['gmres_iter']:.5f}s (30-iteration cycle); combined with the GPU run's per-step counts "
+                           f"{counts}"),
+                "cpu": _cpu_model()}
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    ns = max(1, round(nsub_work * m.nverts / V_work))
+    t = oracle_phase_times(m, ns, ilu_level, overlap, ordering)
     scale = V_work / m.nverts
-    return {"value": per_step * scale, "unit": "s/step", "cores": 1, "kind": "oracle",
+    corr, src = validation_factors(V_work, nsub_work, ilu_level, overlap, ordering)
+    tc = {k: t[k] * scale * corr.get(k, 1.0) for k in ("funceval", "jaceval", "pcsetup", "gmres_iter")}
+    return {"value": per_step(tc, counts), "unit": "s/step", "cores": 1, "kind": "oracle",
+            "uncorrected_value": per_step(t, counts) * scale,
             "sample": (f"oracle phases on the depth-1 tree ({m.nverts} vertices, {ns} subdomains, ILU({ilu_level}), "
-                       f"{ORDERING[ordering]} ordering): "
-                       f"FuncEval {t_fe:.3f}s, JacEval {t_je:.3f}s, PCSetUp {t_ps:.3f}s, GMRES iter {t_it:.4f}s; "
-                       f"combined with the GPU run's per-step counts {counts} and scaled by {scale:.2f} "
-                       f"(vertex ratio)"),
+                       f"{ORDERING[ordering]} ordering): FuncEval {t['funceval']:.3f}s, JacEval {t['jaceval']:.3f}s, "
+                       f"PCSetUp {t['pcsetup']:.3f}s, GMRES iter {t['gmres_iter']:.4f}s (30-iteration cycle); "
+                       f"combined with the GPU run's per-step counts {counts}, extrapolated by {scale:.2f} (vertex "
+                       f"ratio) and by the per-phase factors {corr} by which the oracle on the workload's own mesh "
+                       f"exceeded that extrapolation ({src})"),
             "cpu": _cpu_model()}
 
 
+def validation_factors(V_work, nsub, ilu_level, overlap, ordering):
+    """Per-phase ratios full-mesh / extrapolated sample from the record --validate-cpu-baseline
+    wrote for this configuration (profiles/cpu_baseline_validation_*.json), or none."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "cpu_baseline_validation_*.json"))):
+        try:
+            rec = json.load(open(path))
+        except (OSError, ValueError):
+            continue
+        cfg = rec.get("config", {})
+        if (rec.get("workload_vertices") == V_work and cfg.get("nsub") == nsub and cfg.get("ilu_level") == ilu_level
+                and cfg.get("overlap") == overlap and cfg.get("ordering") == ordering):
+            return rec["full_over_extrapolated"], (f"{os.path.relpath(path, ROOT)}, measured on "
+                                                   f"{rec.get('cpu', 'an unnamed CPU')}")
+    return {}, "no full-mesh record for this configuration: uncorrected"
+
+
+def validate_cpu_baseline(args, counts: dict) -> dict:
+    """The oracle's phases timed on the workload's own mesh against the depth-1 sample scaled
+    by the vertex ratio (CPU only; no GPU needed)."""
+    mesh = W.tree_mesh(depth=args.depth, h=W.TREE_H[args.depth])
+    full = oracle_phase_times(mesh, args.nsub, args.ilu, args.overlap, args.ordering)
+    log(f"[validate] full mesh ({mesh.nverts} vertices): {full}")
+    m1 = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    ns = max(1, round(args.nsub * m1.nverts / mesh.nverts))
+    samp = oracle_phase_times(m1, ns, args.ilu, args.overlap, args.ordering)
+    scale = mesh.nverts / m1.nverts
+    log(f"[validate] sample ({m1.nverts} vertices, {ns} subdomains) x {scale:.3f}: {samp}")
+    ratio = {k: full[k] / (samp[k] * scale) for k in ("funceval", "jaceval", "pcsetup", "gmres_iter")}
+    est, meas = per_step(samp, counts) * scale, per_step(full, counts)
+    return {"workload_vertices": mesh.nverts, "sample_vertices": m1.nverts, "vertex_ratio": round(scale, 4),
+            "sample_subdomains": ns, "config": {"nsub": args.nsub, "ilu_level": args.ilu, "overlap": args.overlap,
+                                                "ordering": args.ordering},
+            "full_mesh_s": {k: round(v, 4) for k, v in full.items()},
+            "sample_s": {k: round(v, 4) for k, v in samp.items()},
+            "full_over_extrapolated": {k: round(v, 3) for k, v in ratio.items()},
+            "counts_per_step": counts, "per_step_extrapolated_s": round(est, 2), "per_step_full_mesh_s": round(meas, 2),
+            "extrapolation_error": round(est / meas - 1.0, 4), "cpu": _cpu_model(), "cores": 1}
+
+
 def _cpu_model() -> str:
+    """Model name of the host CPU with its family/model/stepping numbers (a virtual machine
+    may report only a generic name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k in ("model name", "cpu family", "model", "stepping", "cpu MHz") and k not in info:
+                info[k] = v.strip()
+            if not line.strip() and info:
+                break
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    return (f"{info.get('model name', 'unknown')} (family {info.get('cpu family', '?')}, model {info.get('model', '?')}, "
+            f"stepping {info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz; {os.cpu_count()} logical CPUs)")
 
 
 def main():
@@ -125,9 +198,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=("tree", "tube"), default="tree",
+                    help="tree: the bifurcating compliant tree (default); tube: the straight compliant tube, one "
+                         "backward-Euler step from the Poiseuille state, repeated")
     ap.add_argument("--depth", type=int, default=3)
-    ap.add_argument("--nsub", type=int, default=256)
-    ap.add_argument("--ilu", type=int, default=3)
+    ap.add_argument("--nsub", type=int, default=0, help="Schwarz subdomains (default: 256 tree, 4 tube)")
+    ap.add_argument("--ilu", type=int, default=-1, help="ILU fill level (default: 3 tree, 0 tube)")
     ap.add_argument("--dt", type=float, default=1e-3)
     ap.add_argument("--overlap", type=int, default=1)
     ap.add_argument("--ordering", type=int, default=0, help="subdomain ordering: 0 RCM, 1 one-way dissection")
@@ -143,7 +219,25 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB three times "
                          "(reference dispatch for scaling rocprofv3 byte counters)")
+    ap.add_argument("--validate-cpu-baseline", action="store_true",
+                    help="CPU only: time the oracle's phases on the workload's own mesh and compare them with "
+                         "the extrapolated depth-1 sample; prints one JSON line")
+    ap.add_argument("--allow-divergence", action="store_true",
+                    help="a step that fails ends the run with a JSON line (value null) that records every step's "
+                         "Newton and GMRES iterations, instead of an exception")
+    ap.add_argument("--counts", default="4,3,3,185",
+                    help="per-step FuncEval, JacEval, PCSetUp and GMRES-iteration counts for --validate-cpu-baseline")
     args = ap.parse_args()
+    tube = args.workload == "tube"
+    if args.nsub <= 0:
+        args.nsub = 4 if tube else 256
+    if args.ilu < 0:
+        args.ilu = 0 if tube else 3
+    if args.validate_cpu_baseline:
+        c = [float(x) for x in args.counts.split(",")]
+        counts = dict(funceval=c[0], jaceval=c[1], pcsetup=c[2], gmres_iters=c[3])
+        print(json.dumps(validate_cpu_baseline(args, counts)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library does not "
               "shard the Schwarz subdomains over several GPUs.", file=sys.stderr)
@@ -156,7 +250,7 @@ def main():
     dev = torch.device("cuda", 0)
 
     t0 = time.perf_counter()
-    mesh = W.tree_mesh(depth=args.depth, h=W.TREE_H[args.depth])
+    mesh = W.tube_mesh() if tube else W.tree_mesh(depth=args.depth, h=W.TREE_H[args.depth])
     ph = W.physics_config1()
     opts = dict(nsub=args.nsub, overlap=args.overlap, ilu_level=args.ilu, ordering=args.ordering, jac_lag=args.jac_lag,
                 gmres_restart=30,
@@ -168,34 +262,79 @@ def main():
     log(f"[bench] mesh V={mesh.nverts} E={mesh.ntets} n={s.n} nnzb={s.nnzb} setup {time.perf_counter() - t0:.1f}s")
 
     dt = args.dt
-    nsteps = 2 + args.warmup + args.steps
-    G = [torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak((k + 1) * dt))).to(dev) for k in range(nsteps + 1)]
+    # tree: two rigid-wall steps from rest start the flow, then warmup and timed steps of the
+    # pulsatile inflow; tube: every step is the same backward-Euler step from the Poiseuille
+    # state with the peak inflow 30 cm/s
+    nstart = 0 if tube else 2
+    nsteps = nstart + args.warmup + args.steps
+    if tube:
+        y_start = torch.as_tensor(W.poiseuille_state(mesh, 30.0, ph["mu_f"], 5.0)).to(dev)
+        G = [torch.as_tensor(W.dirichlet_values(mesh, 30.0)).to(dev)] * (nsteps + 1)
+    else:
+        G = [torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak((k + 1) * dt))).to(dev) for k in range(nsteps + 1)]
     rigid = W.rigid_wall_mask(mesh)
     y_old = torch.zeros(s.n, dtype=torch.float64, device=dev)
     y = torch.empty_like(y_old)
+    step_log = []
 
-    def step(k, mask=None):
-        s.set_step((k + 1) * dt, dt, y_old, G[k], None, mask)
+    class StepFailed(Exception):
+        pass
+
+    def step(k, mask=None, phase="timed"):
+        if tube:
+            y_old.copy_(y_start)
+        s.set_step(dt if tube else (k + 1) * dt, dt, y_old, G[k], None, mask)
         y.copy_(y_old)
         st, rc = s.newton_solve(y, check=False)
+        ni = st["newton_iters"]
+        step_log.append({"step": k, "phase": phase, "rc": rc, "converged": st["converged"], "NI": ni,
+                         "LI": st["lin_hist"][:max(ni, 1)], "cap_hits": sum(1 for x in st["lin_hist"][:max(ni, 1)]
+                                                                         if x >= opts["gmres_maxit"]),
+                         "fnorm_ratio": st["fnorm"] / st["fnorm0"] if st["fnorm0"] else 0.0})
         if rc != 0:
+            if args.allow_divergence:
+                raise StepFailed()
             raise RuntimeError(f"step {k} failed with status {rc}: {st}")
         y_old.copy_(y)
         return st
 
-    for k in range(2):
-        st = step(k, rigid)
-        log(f"[bench] rigid start step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
-    for k in range(2, 2 + args.warmup):
-        st = step(k)
-        log(f"[bench] warmup step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
+    def failed_record():
+        return {"metric": METRIC, "value": None, "unit": "s/step", "n_gpus": 1, "steps": args.steps,
+                "warmup": args.warmup, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": workload_name(), "nverts": mesh.nverts, "n": s.n, "nsub": args.nsub,
+                           "ilu_level": args.ilu, "overlap": args.overlap, "ordering": args.ordering},
+                "failed_step": step_log[-1], "step_log": step_log}
+
+    def workload_name():
+        sch = (f"{args.nsub} RAS subdomains overlap {args.overlap}, ILU({args.ilu}), {ORDERING[args.ordering]} ordering, "
+               f"GMRES(30) rtol 1e-3, Newton rtol 1e-6"
+               + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps"}[args.precision])
+        if tube:
+            return (f"straight compliant tube, {mesh.nverts} vertices, {mesh.ntets} tets, {s.n} unknowns, one "
+                    f"backward-Euler step dt {dt} from the Poiseuille state (peak 30 cm/s), {sch}")
+        return (f"bifurcating compliant tree depth {args.depth}, {mesh.nverts} vertices, {mesh.ntets} tets, {s.n} "
+                f"unknowns, dt {dt}, {sch}")
+
+    try:
+        for k in range(nstart):
+            st = step(k, rigid, "rigid start")
+            log(f"[bench] rigid start step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
+        for k in range(nstart, nstart + args.warmup):
+            st = step(k, None, "warmup")
+            log(f"[bench] warmup step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
+    except StepFailed:
+        log(f"[bench] step failed: {step_log[-1]}")
+        print(json.dumps(failed_record()), flush=True)
+        s.close()
+        return
 
     tune = None
     if args.sweep_mb:
         s.pc_select(args.sweep_mb)
         tune = {"best_blocks_per_task": args.sweep_mb, "selected": True}
         log(f"[bench] sweep schedule selected: {args.sweep_mb} blocks per task")
-    elif not args.no_tune:  # sweep schedule timed on the last step's factors, outside the timed steps
+    elif not args.no_tune and nstart + args.warmup > 0:  # sweep schedule timed on the last step's factors,
+        # outside the timed steps
         best, us = s.pc_tune(3)
         tune = {"best_blocks_per_task": best, "us_per_apply": {str(k): round(v, 1) for k, v in us.items()}}
         log(f"[bench] sweep schedule: {tune}")
@@ -214,10 +353,16 @@ def main():
     torch.cuda.synchronize()
     stats = []
     t_start = time.perf_counter()
-    for k in range(2 + args.warmup, nsteps):
-        stats.append(step(k))
-        log(f"[bench] step {k}: NI {stats[-1]['newton_iters']} LI {stats[-1]['lin_hist'][:stats[-1]['newton_iters']]} "
-            f"cuts {stats[-1]['line_search_cuts']}")
+    try:
+        for k in range(nstart + args.warmup, nsteps):
+            stats.append(step(k))
+            log(f"[bench] step {k}: NI {stats[-1]['newton_iters']} LI {stats[-1]['lin_hist'][:stats[-1]['newton_iters']]} "
+                f"cuts {stats[-1]['line_search_cuts']}")
+    except StepFailed:
+        log(f"[bench] step failed: {step_log[-1]}")
+        print(json.dumps(failed_record()), flush=True)
+        s.close()
+        return
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     sec_per_step = elapsed / args.steps
@@ -227,7 +372,7 @@ def main():
         torch.cuda.synchronize()
 
     kernels = {}
-    for name in ("ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid", "jac_gather",
+    for name in ("ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid", "jac_init",
                  "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate", "vupdate_mdot",
                  "vupdate_sqnorm"):
         ms, cnt = s.prof_get(name)
@@ -261,10 +406,7 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": {0: "f64", 1: "f64 (f32 Schwarz sweeps)", 2: "f64 (bf16 factors, f32 Schwarz sweeps)"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"bifurcating compliant tree depth {args.depth}, {mesh.nverts} vertices, "
-                               f"{mesh.ntets} tets, {s.n} unknowns, dt {dt}, {args.nsub} RAS subdomains overlap {args.overlap}, "
-                               f"ILU({args.ilu}), {ORDERING[args.ordering]} ordering, GMRES(30) rtol 1e-3, Newton rtol 1e-6"
-                               + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps"}[args.precision],
+        "config": {"workload": workload_name(),
                    "nverts": mesh.nverts, "ntets": mesh.ntets, "n": s.n, "nnzb": s.nnzb, "nsub": args.nsub,
                    "ilu_level": args.ilu, "overlap": args.overlap, "ordering": args.ordering, "jac_lag": args.jac_lag,
                    "dt": dt, "local_blocks": sw["local_blocks"],
@@ -281,11 +423,16 @@ def main():
         "spmv": {"achieved_GBs": round(spmv_gbs, 1) if spmv_gbs else None, "bytes": sb,
                  "frac": round(spmv_gbs / HBM_PEAK, 4) if spmv_gbs else None},
         "kernels": kernels,
+        "step_log": step_log,
     }
-    if args.precision != 0:
+    if tube:
+        out["roofline"]["note"] = ("the tube's matrix and factors (about 20 MB) stay in the caches: an in-cache "
+                                   "rate, not an HBM figure")
+    if args.precision != 0 and not tube:
         out["error_vs_fp64"] = error_vs_fp64(s, fsi, mesh, ph, opts, G, rigid, dt, nsteps, dev)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap, args.ordering)
+        out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap, args.ordering,
+                                           small_mesh=mesh if tube else None)
     print(json.dumps(out), flush=True)
     s.close()
 

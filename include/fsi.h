@@ -129,6 +129,10 @@ typedef struct fsi_solver fsi_solver;
 fsi_status fsi_create(const fsi_mesh *mesh, const fsi_physics *phys, const fsi_opts *opts,
                       void *hip_stream, fsi_solver **out);
 fsi_status fsi_destroy(fsi_solver *s);
+/* Sizes of the discrete problem: n = 7 nverts unknowns (the state y of §2.2 eq. (8), one
+ * 7-vector per vertex) and nnzb, the number of 7x7 blocks of the Jacobian of eq. (12)
+ * (vertex pairs that share a tetrahedron, plus the diagonal).  Either pointer (host) may
+ * be NULL.  Error ARG on a NULL solver. */
 fsi_status fsi_sizes(const fsi_solver *s, int64_t *n, int64_t *nnzb);
 const char *fsi_last_error(const fsi_solver *s);
 
@@ -155,11 +159,14 @@ fsi_status fsi_jacobian_get(const fsi_solver *s, int32_t *rowptr /* host, nverts
                             int32_t *colind /* host, nnzb */, double *vals /* host, nnzb*49 */);
 
 /* Replace the values of the solver's block matrix by caller-supplied ones (same pattern as
- * fsi_jacobian_get reports), e.g. a Jacobian assembled elsewhere.  Marks the matrix ready
- * for fsi_spmv / fsi_pc_setup. */
+ * fsi_jacobian_get reports): a Jacobian of eq. (12) assembled elsewhere, for instance to
+ * apply and factor exactly the same matrix as another implementation.  Marks the matrix
+ * ready for fsi_spmv / fsi_pc_setup.  Error ARG on a NULL pointer. */
 fsi_status fsi_jacobian_set(fsi_solver *s, const double *vals /* host, nnzb*49 */);
 
-/* y = J x with the current Jacobian. */
+/* y = J x with the current Jacobian: the matrix-vector product of each GMRES iteration on
+ * the preconditioned Jacobian system (§3 eqs. (12)-(13)).  Rows of the block CSR are
+ * summed in ascending column order.  Error ARG before a Jacobian exists. */
 fsi_status fsi_spmv(fsi_solver *s, const double *x /* dev, n */, double *y /* dev, n */);
 
 /* Schwarz setup (§3 eqs. (15)-(16)): gather every subdomain matrix from J and factor it
@@ -205,15 +212,24 @@ fsi_status fsi_pc_select(fsi_solver *s, int32_t mb);
  * not measured separately.  Default off. */
 fsi_status fsi_set_graphs(fsi_solver *s, int32_t on);
 
-/* Right-preconditioned restarted GMRES on J x = rhs from x0 = 0 (classical Gram-Schmidt
- * twice, Givens rotations).  Non-convergence is reported in st->converged, not as an
- * error. */
+/* GMRES on J x = rhs (§3 eq. (12)), preconditioned from the right by the Schwarz
+ * operator B^{-1} of eq. (16) as eq. (13) allows ("GMRES(fGMRES)", §4 set-up): restarted
+ * every gmres_restart iterations, from x0 = 0, classical Gram-Schmidt applied twice,
+ * Givens rotations, stopping when the residual estimate reaches gmres_rtol ||rhs|| (the
+ * paper's linear tolerance, 1e-3 by default) or after gmres_maxit iterations.
+ * Non-convergence is reported in st->converged, not as an error.  Error ARG before the
+ * preconditioner exists; HIP if a sweep exceeded its wait bound. */
 fsi_status fsi_gmres(fsi_solver *s, const double *rhs /* dev, n */, double *x /* dev, n */,
                      fsi_lin_stats *st /* host, may be NULL */);
 
-/* One implicit step: Newton from the guess y (Dirichlet values imposed first) to
- * ||F|| <= max(newton_rtol ||F_0||, newton_atol).  y (dev, n) is overwritten with the
- * result.  Error DIVERGED if the iteration limit is hit or the line search fails. */
+/* One implicit step: inexact Newton with backtracking (§3 eq. (11)) on F(y) = 0 of
+ * eq. (10), from the guess y (Dirichlet values imposed first) to
+ * ||F|| <= max(newton_rtol ||F_0||, newton_atol) (the paper's nonlinear tolerance 1e-6,
+ * §4 set-up).  Each Newton direction comes from fsi_gmres on eq. (12); the Jacobian and
+ * the Schwarz factors are rebuilt every jac_lag iterations (§4.4); the line search halves
+ * the step until the Armijo condition holds (an inverted element counts as a rejection).
+ * y (dev, n) is overwritten with the result.  Error DIVERGED if the iteration limit is hit
+ * or the line search fails. */
 fsi_status fsi_newton_solve(fsi_solver *s, double *y, fsi_step_stats *st /* host, may be NULL */);
 
 /* Replace the Newton tolerances of fsi_opts (rtol >= 0, atol >= 0, not both 0) for the
@@ -248,7 +264,7 @@ fsi_status fsi_pc_get(const fsi_solver *s, int32_t *part, int32_t *sub_ptr, int3
  * fsi_prof_enable(s, 1) starts recording an event pair around every launch of the timed
  * kernels; fsi_prof_get returns the summed duration (ms) and launch count for a kernel
  * name: "ilu_fwd", "ilu_bwd", "ilu_factor", "spmv", "elem_jac_fluid", "elem_jac_solid",
- * "jac_gather", "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate". */
+ * "jac_init", "elem_res_fluid", "elem_res_solid", "res_gather", "mdot", "vupdate". */
 fsi_status fsi_prof_enable(fsi_solver *s, int32_t on);
 fsi_status fsi_prof_get(fsi_solver *s, const char *kernel, double *total_ms, int64_t *count);
 
