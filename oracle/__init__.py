@@ -96,6 +96,7 @@ def lib():
             "fsio_gmres": [vp, vp, vp, vp], "fsio_newton_solve": [vp, vp, vp],
             "fsio_topology_get": [vp, vp, vp, vp, vp], "fsio_pc_sizes": [vp, vp, vp, vp, vp],
             "fsio_pc_get": [vp] + [vp] * 9, "fsio_element": [vp, vp, i32, vp, vp],
+            "fsio_element_ops": [vp, vp, i32, vp, vp],
         }
         for k, a in sig.items():
             f = getattr(L, k)
@@ -263,6 +264,13 @@ class Oracle:
                                                            "udiag")])
         out["nlevels_total"] = nl.value
         return out
+
+    def element_ops(self, y, e):
+        """(value operations, tangent operations per forward-mode direction) of element e."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        v, t = C.c_int64(), C.c_int64()
+        self._chk(lib().fsio_element_ops(self.h, _p(y), int(e), C.byref(v), C.byref(t)), "element_ops")
+        return v.value, t.value
 
     def element(self, y, e):
         y = np.ascontiguousarray(y, dtype=np.float64)

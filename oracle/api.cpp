@@ -205,4 +205,9 @@ int fsio_element(fsio_solver* s, const double* y, int32_t e, double* Re, double*
   return element(*s, y, e, Re, Je);
 }
 
+int fsio_element_ops(fsio_solver* s, const double* y, int32_t e, int64_t* value_ops, int64_t* tangent_ops) {
+  if (!s || !y || !value_ops || !tangent_ops || e < 0 || e >= s->E || !s->has_step) return FSIO_ERR_ARG;
+  return element_ops(*s, y, e, value_ops, tangent_ops);
+}
+
 }  // extern "C"

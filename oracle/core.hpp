@@ -51,6 +51,56 @@ template <int N> inline Dual<N>& operator-=(Dual<N>& a, const Dual<N>& b) { a = 
 template <int N> inline Dual<N> sqrt(const Dual<N>& a) {
   Dual<N> r; r.v = std::sqrt(a.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] / (2.0 * r.v); return r; }
 
+// Counting scalar (measurement only): a value that counts the arithmetic done on it and
+// knows whether it depends on the element's unknowns.  value: operations of one plain
+// evaluation; tangent: operations each forward-mode direction adds (a + b and a * c with
+// one dependent operand: 1 and 1; a * b with both dependent: 3; a / b: 1 if only a
+// depends, 2 if only b, 3 if both; sqrt: 1 per direction).  Unary minus is not counted.
+struct OpCount {
+  int64_t value = 0, tangent = 0;
+};
+extern thread_local OpCount g_ops;
+struct Fl {
+  double v;
+  bool dep;
+  Fl() : v(0.0), dep(false) {}
+  Fl(double x, bool d = false) : v(x), dep(d) {}
+};
+inline Fl fl_add(const Fl& a, const Fl& b, double v) {
+  g_ops.value++;
+  if (a.dep && b.dep) g_ops.tangent++;
+  return Fl(v, a.dep || b.dep);
+}
+inline Fl operator+(const Fl& a, const Fl& b) { return fl_add(a, b, a.v + b.v); }
+inline Fl operator-(const Fl& a, const Fl& b) { return fl_add(a, b, a.v - b.v); }
+inline Fl operator-(const Fl& a) { return Fl(-a.v, a.dep); }
+inline Fl operator*(const Fl& a, const Fl& b) {
+  g_ops.value++;
+  g_ops.tangent += (a.dep && b.dep) ? 3 : (a.dep || b.dep) ? 1 : 0;
+  return Fl(a.v * b.v, a.dep || b.dep);
+}
+inline Fl operator/(const Fl& a, const Fl& b) {
+  g_ops.value++;
+  g_ops.tangent += (a.dep && b.dep) ? 3 : b.dep ? 2 : a.dep ? 1 : 0;
+  return Fl(a.v / b.v, a.dep || b.dep);
+}
+inline Fl operator+(const Fl& a, double b) { return a + Fl(b); }
+inline Fl operator+(double a, const Fl& b) { return Fl(a) + b; }
+inline Fl operator-(const Fl& a, double b) { return a - Fl(b); }
+inline Fl operator-(double a, const Fl& b) { return Fl(a) - b; }
+inline Fl operator*(const Fl& a, double b) { return a * Fl(b); }
+inline Fl operator*(double a, const Fl& b) { return Fl(a) * b; }
+inline Fl operator/(const Fl& a, double b) { return a / Fl(b); }
+inline Fl operator/(double a, const Fl& b) { return Fl(a) / b; }
+inline Fl& operator+=(Fl& a, const Fl& b) { a = a + b; return a; }
+inline Fl& operator-=(Fl& a, const Fl& b) { a = a - b; return a; }
+inline Fl sqrt(const Fl& a) {
+  g_ops.value++;
+  if (a.dep) g_ops.tangent++;
+  return Fl(std::sqrt(a.v), a.dep);
+}
+inline double val(const Fl& x) { return x.v; }
+
 inline double val(double x) { return x; }
 inline double val(const std::complex<double>& x) { return x.real(); }
 template <int N> inline double val(const Dual<N>& x) { return x.v; }
@@ -125,6 +175,7 @@ int residual(fsio_solver& s, const double* y, double* F);
 int residual_complex(fsio_solver& s, const Cplx* y, Cplx* F);
 int jacobian(fsio_solver& s, const double* y);
 int element(fsio_solver& s, const double* y, int e, double* Re, double* Je);
+int element_ops(fsio_solver& s, const double* y, int e, int64_t* value_ops, int64_t* tangent_ops);
 
 void rcb_partition(const fsio_solver& s, int nsub, std::vector<int>& part);
 int build_subdomains(fsio_solver& s);

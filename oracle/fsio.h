@@ -99,6 +99,11 @@ int fsio_pc_get(const fsio_solver *s, int32_t *part, int32_t *sub_ptr, int32_t *
                 double *factors, double *udiag);
 /* element-level access for pins: element residual (28) and dual-number Jacobian (28x28) */
 int fsio_element(fsio_solver *s, const double *y, int32_t e, double *Re, double *Je);
+/* operation counts of element e's residual at y (measurement): value_ops, the operations of
+ * one evaluation (its algorithmic flops); tangent_ops, the operations one forward-mode
+ * derivative direction adds; the exact element Jacobian by forward mode costs
+ * value_ops + 28 tangent_ops */
+int fsio_element_ops(fsio_solver *s, const double *y, int32_t e, int64_t *value_ops, int64_t *tangent_ops);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,8 @@
 
 namespace fsio {
 
+thread_local OpCount g_ops;
+
 static const double kQa = (5.0 + 3.0 * std::sqrt(5.0)) / 20.0;  // barycentric weight of the own vertex
 static const double kQb = (5.0 - std::sqrt(5.0)) / 20.0;        // weight of the other three
 
@@ -69,9 +71,11 @@ static T p1_gradients(const T x[4][3], T gr[4][3], T Jxi[3][3]) {
 }
 
 // Fluid element: rows [4][0..2] momentum, [4][3] continuity, [4][4..6] mesh Laplace.
-template <class T>
-static bool fluid_element(const Phys& ph, double dt, const double X[4][3], const T y[4][7],
-                          const double yo[4][7], const double f[4][3], T R[4][7]) {
+// T: the unknowns' scalar; D: the data's (reference coordinates, old state, body force),
+// double except when the operations are counted.
+template <class T, class D>
+static bool fluid_element(const Phys& ph, double dt, const D X[4][3], const T y[4][7],
+                          const D yo[4][7], const D f[4][3], T R[4][7]) {
   const double rho = ph.rho_f, mu = ph.mu_f, nu = mu / rho;
   T x[4][3], w[4][3];
   for (int a = 0; a < 4; ++a)
@@ -122,10 +126,10 @@ static bool fluid_element(const Phys& ph, double dt, const double X[4][3], const
     double lam[4];
     for (int a = 0; a < 4; ++a) lam[a] = (a == q) ? kQa : kQb;
     T uq[3], wq[3], cq[3];
-    double uoq[3], fq[3];
+    D uoq[3], fq[3];
     for (int i = 0; i < 3; ++i) {
       T su = 0.0, sw = 0.0;
-      double so = 0.0, sf = 0.0;
+      D so = 0.0, sf = 0.0;
       for (int a = 0; a < 4; ++a) {
         su += lam[a] * y[a][i];
         sw += lam[a] * w[a][i];
@@ -161,14 +165,14 @@ static bool fluid_element(const Phys& ph, double dt, const double X[4][3], const
     }
 
   // harmonic mesh extension on the reference configuration
-  double X0[4][3], gr0[4][3], Jxi0[3][3];
+  D X0[4][3], gr0[4][3], Jxi0[3][3];
   for (int a = 0; a < 4; ++a)
     for (int i = 0; i < 3; ++i) X0[a][i] = X[a][i];
-  double det0 = p1_gradients(X0, gr0, Jxi0);
-  double vol0 = det0 / 6.0;
+  D det0 = p1_gradients(X0, gr0, Jxi0);
+  D vol0 = det0 / 6.0;
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) {
-      double kab = vol0 * (gr0[a][0] * gr0[b][0] + gr0[a][1] * gr0[b][1] + gr0[a][2] * gr0[b][2]);
+      D kab = vol0 * (gr0[a][0] * gr0[b][0] + gr0[a][1] * gr0[b][1] + gr0[a][2] * gr0[b][2]);
       for (int i = 0; i < 3; ++i) R[a][4 + i] += kab * y[b][4 + i];
     }
 
@@ -178,14 +182,14 @@ static bool fluid_element(const Phys& ph, double dt, const double X[4][3], const
 }
 
 // Solid element (total Lagrangian on the reference configuration): rows [4][0..2].
-template <class T>
-static bool solid_element(const Phys& ph, double dt, const double X[4][3], const T y[4][7],
-                          const double yo[4][7], const double f[4][3], T R[4][7]) {
+template <class T, class D>
+static bool solid_element(const Phys& ph, double dt, const D X[4][3], const T y[4][7],
+                          const D yo[4][7], const D f[4][3], T R[4][7]) {
   const double mus = ph.E_s / (2.0 * (1.0 + ph.nu_s));
   const double lams = ph.E_s * ph.nu_s / ((1.0 + ph.nu_s) * (1.0 - 2.0 * ph.nu_s));
-  double gr0[4][3], Jxi0[3][3];
-  double det0 = p1_gradients(X, gr0, Jxi0);
-  double vol0 = det0 / 6.0;
+  D gr0[4][3], Jxi0[3][3];
+  D det0 = p1_gradients(X, gr0, Jxi0);
+  D vol0 = det0 / 6.0;
   T F[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) {
@@ -221,7 +225,7 @@ static bool solid_element(const Phys& ph, double dt, const double X[4][3], const
     for (int a = 0; a < 4; ++a) lam[a] = (a == q) ? kQa : kQb;
     for (int i = 0; i < 3; ++i) {
       T uq = 0.0;
-      double uoq = 0.0, fq = 0.0;
+      D uoq = 0.0, fq = 0.0;
       for (int a = 0; a < 4; ++a) {
         uq += lam[a] * y[a][i];
         uoq += lam[a] * yo[a][i];
@@ -356,6 +360,29 @@ int jacobian(fsio_solver& s, const double* y) {
   }
   s.jac_ready = true;
   return FSIO_OK;
+}
+
+// Operations of element e's residual at y, counted by the counting scalar: value
+// operations (the residual's algorithmic flops) and tangent operations per forward-mode
+// direction (what each of the 28 Jacobian columns adds on top of one value pass).
+int element_ops(fsio_solver& s, const double* yv, int e, int64_t* value_ops, int64_t* tangent_ops) {
+  Fl X[4][3], yo[4][7], f[4][3], y[4][7], R[4][7];
+  for (int a = 0; a < 4; ++a) {
+    int v = s.tets[4 * e + a];
+    for (int i = 0; i < 3; ++i) {
+      X[a][i] = Fl(s.X[3 * (size_t)v + i]);
+      f[a][i] = Fl(s.bforce.empty() ? 0.0 : s.bforce[3 * (size_t)v + i]);
+    }
+    for (int r = 0; r < 7; ++r) {
+      y[a][r] = Fl(yv[7 * (size_t)v + r], true);
+      yo[a][r] = Fl(s.yold[7 * (size_t)v + r]);
+    }
+  }
+  g_ops = OpCount{};
+  bool ok = s.dom[e] == 0 ? fluid_element(s.ph, s.dt, X, y, yo, f, R) : solid_element(s.ph, s.dt, X, y, yo, f, R);
+  *value_ops = g_ops.value;
+  *tangent_ops = g_ops.tangent;
+  return ok ? FSIO_OK : FSIO_ERR_INVERTED;
 }
 
 int element(fsio_solver& s, const double* y, int e, double* Re, double* Je) {

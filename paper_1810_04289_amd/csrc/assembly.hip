@@ -9,14 +9,17 @@
 // residual vanishes for linear elements.  Quadrature: 4-point degree-2 rule for the fluid
 // terms and all mass terms, exact single-point integration for constant integrands.
 //
-// Scatter: each element writes its 28-row residual (or its 28x28 element matrix) to a
-// staging buffer; gather kernels then sum, per degree of freedom (or per block entry),
-// the contributions of the incident elements in ascending element order.  No atomics, and
-// the result is bitwise reproducible from run to run.
+// Residual scatter: each element writes its 28-row residual to a staging buffer; a gather
+// kernel then sums, per degree of freedom, the contributions of the incident elements in
+// ascending element order.
 //
 // Jacobian: exact (§3, no finite differences).  Lane j of a 32-lane team evaluates the
 // element residual in dual numbers seeded with the j-th element unknown, so one team
-// produces the 28 columns of the element matrix at once.
+// produces the 28 columns of the element matrix at once, in registers, and adds column j
+// straight into the 16 blocks of J the element touches.  Elements are coloured so that no
+// two of one colour share a vertex; one launch per colour then updates disjoint entries of
+// J, without atomics.  The sums follow the colour order, fixed at set-up, so the result is
+// bitwise reproducible from run to run.
 #include "fsi_internal.hpp"
 
 namespace fsi {
@@ -290,29 +293,84 @@ __global__ void __launch_bounds__(256) k_elem_res(PhysDev P, int nel, const int3
 }
 
 // ---- JacEval: a 32-lane team per element, lane j = column j of the element matrix ----------
+// elems: the elements of one colour (no two share a vertex).  A wavefront holds two
+// elements.  For each local row vertex a in turn, the two teams write block row a of their
+// element matrices (columns j = 7 b + c of rows 7 a + r) to the wavefront's LDS stage, and
+// the wavefront then adds the stage to the blocks (a, b) of J on equation rows, 49
+// consecutive entries per block, so that consecutive lanes update consecutive doubles.
 template <int KIND>
 __global__ void __launch_bounds__(256) k_elem_jac(PhysDev P, int nel, const int32_t* __restrict__ elems,
                                                   const int32_t* __restrict__ tets, const double* __restrict__ X,
                                                   const double* __restrict__ y, const double* __restrict__ yold,
-                                                  const double* __restrict__ bf, double* __restrict__ elemJ,
+                                                  const double* __restrict__ bf, const int32_t* __restrict__ elem_blk,
+                                                  const uint8_t* __restrict__ rowkind, double* __restrict__ vals,
                                                   int32_t* __restrict__ flags) {
+  __shared__ double stage[4][2 * 4 * 49];  // per wavefront: [element of the pair][b][7 r + c]
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = gt >> 5;
   const int j = gt & 31;
-  if (t >= nel) return;
-  const int e = elems[t];
+  const int lane = threadIdx.x & 63, half = lane >> 5, wv = threadIdx.x >> 6;
+  const bool live = t < nel;
+  const int e = live ? elems[t] : 0;
   double Xe[4][3], yo[4][7], fe[4][3];
   int vid[4];
-  load_elem<KIND>(e, tets, X, yold, bf, Xe, yo, fe, vid);
-  DN ye[4][7], R[4][7];
-  for (int a = 0; a < 4; ++a)
-    for (int r = 0; r < 7; ++r) ye[a][r] = DN{y[7 * (size_t)vid[a] + r], (7 * a + r == j) ? 1.0 : 0.0};
-  bool ok = KIND == 0 ? fluid_elem<DN>(P, Xe, ye, yo, fe, R) : solid_elem<DN>(P, Xe, ye, yo, fe, R);
-  if (!ok && j == 0) atomicOr(&flags[0], 1);
-  if (j < 28) {
-    double* out = elemJ + 784 * (size_t)e + j;
+  DN R[4][7];
+  if (live) {
+    load_elem<KIND>(e, tets, X, yold, bf, Xe, yo, fe, vid);
+    DN ye[4][7];
     for (int a = 0; a < 4; ++a)
-      for (int r = 0; r < 7; ++r) out[28 * (7 * a + r)] = R[a][r].t;
+      for (int r = 0; r < 7; ++r) ye[a][r] = DN{y[7 * (size_t)vid[a] + r], (7 * a + r == j) ? 1.0 : 0.0};
+    bool ok = KIND == 0 ? fluid_elem<DN>(P, Xe, ye, yo, fe, R) : solid_elem<DN>(P, Xe, ye, yo, fe, R);
+    if (!ok && j == 0) atomicOr(&flags[0], 1);
+  }
+  // scatter metadata of the wavefront's two elements: their 16 blocks of J and, per local
+  // row vertex a and row r, whether that row is an equation row
+  __shared__ int mblk[4][2][16];
+  __shared__ int mrow[4][2][4][8];
+  const int t0 = (gt >> 6) << 1;  // first element of this wavefront
+  {
+    const int el = lane >> 5, k = lane & 31;
+    const int tt = t0 + el;
+    if (tt < nel) {
+      const int ee = elems[tt];
+      if (k < 16) mblk[wv][el][k] = elem_blk[16 * (size_t)ee + k];
+      if (k < 28) {
+        const int a = k / 7, r = k - 7 * a;
+        mrow[wv][el][a][r] = rowkind[7 * (size_t)tets[4 * (size_t)ee + a] + r] == RK_ELEM;
+      }
+    } else {
+      if (k < 28) mrow[wv][el][k / 7][k % 7] = 0;
+      if (k < 16) mblk[wv][el][k] = 0;
+    }
+  }
+  double* st = stage[wv];
+  for (int a = 0; a < 4; ++a) {
+    if (live && j < 28) {
+      const int b = j / 7, c = j - 7 * b;
+#pragma unroll
+      for (int r = 0; r < 7; ++r) st[half * 196 + b * 49 + 7 * r + c] = R[a][r].t;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 392 entries (two elements x four blocks x 49) over the 64 lanes: all loads first
+    size_t off[7];
+    bool use[7];
+    double v[7];
+#pragma unroll
+    for (int it = 0; it < 7; ++it) {
+      const int idx = lane + 64 * it < 392 ? lane + 64 * it : 0;  // past the end: entry 0, unused
+      const int el = idx >= 196, rem = idx - 196 * el, b = rem / 49, ent = rem - 49 * b, r = ent / 7;
+      use[it] = lane + 64 * it < 392 && mrow[wv][el][a][r];
+      off[it] = 49 * (size_t)mblk[wv][el][4 * a + b] + ent;
+      v[it] = use[it] ? vals[off[it]] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < 7; ++it)
+      if (use[it]) vals[off[it]] = v[it] + st[lane + 64 * it];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -343,13 +401,12 @@ __global__ void __launch_bounds__(256) k_res_gather(int64_t n, const uint8_t* __
   F[i] = out;
 }
 
-__global__ void __launch_bounds__(256) k_jac_gather(int64_t nnzb, const int32_t* __restrict__ blkrow,
-                                                    const int32_t* __restrict__ colind,
-                                                    const uint8_t* __restrict__ rowkind,
-                                                    const int32_t* __restrict__ bctr_ptr,
-                                                    const int32_t* __restrict__ bctr,
-                                                    const double* __restrict__ elemJ, double dt,
-                                                    double* __restrict__ vals) {
+// Before the element launches: 0 on equation rows, the nodal rows' entries elsewhere
+// (identity on Dirichlet and dummy rows; d - dt u on kinematic rows, scaled as F).
+__global__ void __launch_bounds__(256) k_jac_init(int64_t nnzb, const int32_t* __restrict__ blkrow,
+                                                  const int32_t* __restrict__ colind,
+                                                  const uint8_t* __restrict__ rowkind, double dt,
+                                                  double* __restrict__ vals) {
   int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= nnzb * 49) return;
   const int64_t k = gid / 49;
@@ -357,13 +414,7 @@ __global__ void __launch_bounds__(256) k_jac_gather(int64_t nnzb, const int32_t*
   const int a = blkrow[k];
   const uint8_t kind = rowkind[7 * (size_t)a + r];
   double out = 0.0;
-  if (kind == RK_ELEM) {
-    for (int p = bctr_ptr[k]; p < bctr_ptr[k + 1]; ++p) {
-      int code = bctr[p];
-      int e = code >> 4, la = (code >> 2) & 3, lb = code & 3;
-      out += elemJ[784 * (size_t)e + 28 * (7 * la + r) + 7 * lb + c];
-    }
-  } else if (colind[k] == a) {
+  if (kind != RK_ELEM && colind[k] == a) {
     if (kind == RK_KIN) out = (c == r) ? 1.0 : (c == r - 4 ? -dt : 0.0);
     else out = (c == r) ? 1.0 : 0.0;
   }
@@ -407,20 +458,29 @@ hipError_t launch_residual(fsi_solver* s, const double* y, double* F) {
 
 hipError_t launch_jacobian(fsi_solver* s, const double* y) {
   const PhysDev P = phys_dev(s);
-  const int nf = (int)s->h.fluid_elems.size(), nsd = (int)s->h.solid_elems.size();
   const double* bf = s->has_bforce ? s->bforce : nullptr;
-  if (nf > 0)
-    FSI_PROF_LAUNCH(s, "elem_jac_fluid",
-                    hipLaunchKernelGGL(k_elem_jac<0>, dim3(nblk((int64_t)nf * 32, 256)), dim3(256), 0, s->stream,
-                                       P, nf, s->fluid_elems, s->tets, s->X, y, s->yold, bf, s->elemJ, s->flags));
-  if (nsd > 0)
-    FSI_PROF_LAUNCH(s, "elem_jac_solid",
-                    hipLaunchKernelGGL(k_elem_jac<1>, dim3(nblk((int64_t)nsd * 32, 256)), dim3(256), 0, s->stream,
-                                       P, nsd, s->solid_elems, s->tets, s->X, y, s->yold, bf, s->elemJ, s->flags));
-  FSI_PROF_LAUNCH(s, "jac_gather",
-                  hipLaunchKernelGGL(k_jac_gather, dim3(nblk(s->nnzb * 49, 256)), dim3(256), 0, s->stream,
-                                     s->nnzb, s->blkrow, s->colind, s->rowkind, s->bctr_ptr, s->bctr, s->elemJ,
-                                     s->dt, s->vals));
+  FSI_PROF_LAUNCH(s, "jac_init",
+                  hipLaunchKernelGGL(k_jac_init, dim3(nblk(s->nnzb * 49, 256)), dim3(256), 0, s->stream, s->nnzb,
+                                     s->blkrow, s->colind, s->rowkind, s->dt, s->vals));
+  // one launch per colour, fluid colours then wall colours
+  const std::vector<int32_t>& fc = s->h.fluid_col;
+  for (size_t c = 0; c + 1 < fc.size(); ++c) {
+    const int n = fc[c + 1] - fc[c];
+    if (n > 0)
+      FSI_PROF_LAUNCH(s, "elem_jac_fluid",
+                      hipLaunchKernelGGL(k_elem_jac<0>, dim3(nblk((int64_t)n * 32, 256)), dim3(256), 0, s->stream, P,
+                                         n, s->fluid_celems + fc[c], s->tets, s->X, y, s->yold, bf, s->elem_blk,
+                                         s->rowkind, s->vals, s->flags));
+  }
+  const std::vector<int32_t>& sc = s->h.solid_col;
+  for (size_t c = 0; c + 1 < sc.size(); ++c) {
+    const int n = sc[c + 1] - sc[c];
+    if (n > 0)
+      FSI_PROF_LAUNCH(s, "elem_jac_solid",
+                      hipLaunchKernelGGL(k_elem_jac<1>, dim3(nblk((int64_t)n * 32, 256)), dim3(256), 0, s->stream, P,
+                                         n, s->solid_celems + sc[c], s->tets, s->X, y, s->yold, bf, s->elem_blk,
+                                         s->rowkind, s->vals, s->flags));
+  }
   return hipGetLastError();
 }
 

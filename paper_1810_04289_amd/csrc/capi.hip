@@ -497,16 +497,16 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->tets = upload(s, h.tets);
   s->fluid_elems = upload(s, h.fluid_elems);
   s->solid_elems = upload(s, h.solid_elems);
+  s->fluid_celems = upload(s, h.fluid_celems);
+  s->solid_celems = upload(s, h.solid_celems);
   s->vinc_ptr = upload(s, h.vinc_ptr);
   s->vinc = upload(s, h.vinc);
-  s->bctr_ptr = upload(s, h.bctr_ptr);
-  s->bctr = upload(s, h.bctr);
+  s->elem_blk = upload(s, h.elem_blk);
   s->rowptr = upload(s, h.rowptr);
   s->colind = upload(s, h.colind);
   s->blkrow = upload(s, blkrow);
   s->vals = dalloc<double>(s, (size_t)s->nnzb * 49);
   s->elemR = dalloc<double>(s, (size_t)h.E * 28);
-  s->elemJ = dalloc<double>(s, (size_t)h.E * 784);
   s->rowkind = dalloc<uint8_t>(s, s->n);
   s->gval = dalloc<double>(s, s->n);
   s->yold = dalloc<double>(s, s->n);

@@ -34,9 +34,12 @@ struct HostSetup {
   std::vector<int32_t> iface;  // [n_iface][3]
 
   std::vector<int32_t> rowptr, colind;          // block pattern
-  std::vector<int32_t> fluid_elems, solid_elems;
+  // fluid and wall elements in ascending order (residual), and each kind grouped by colour
+  // (Jacobian): no two elements of one colour share a vertex; colour c of the fluid is
+  // fluid_celems[fluid_col[c] .. fluid_col[c+1])
+  std::vector<int32_t> fluid_elems, solid_elems, fluid_celems, solid_celems, fluid_col, solid_col;
   std::vector<int32_t> vinc_ptr, vinc;          // vertex -> (e*4 + local) ascending e
-  std::vector<int32_t> bctr_ptr, bctr;          // block -> (e*16 + la*4 + lb) ascending e
+  std::vector<int32_t> elem_blk;                // [E][16]: block of J of (local a, local b)
 
   // Schwarz subdomains (concatenated; a "local row" is one vertex of one subdomain)
   int ns = 0;
@@ -118,10 +121,11 @@ struct fsi_solver {
   // mesh and maps
   double* X = nullptr;
   int32_t *tets = nullptr, *fluid_elems = nullptr, *solid_elems = nullptr;
-  int32_t *vinc_ptr = nullptr, *vinc = nullptr, *bctr_ptr = nullptr, *bctr = nullptr;
+  int32_t *fluid_celems = nullptr, *solid_celems = nullptr;
+  int32_t *vinc_ptr = nullptr, *vinc = nullptr, *elem_blk = nullptr;
   int32_t *rowptr = nullptr, *colind = nullptr, *blkrow = nullptr;
   double* vals = nullptr;
-  double *elemR = nullptr, *elemJ = nullptr;
+  double* elemR = nullptr;
   // step data
   uint8_t* rowkind = nullptr;
   double *gval = nullptr, *yold = nullptr, *bforce = nullptr;

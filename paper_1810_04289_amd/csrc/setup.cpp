@@ -108,10 +108,7 @@ std::string build_topology(HostSetup& h) {
     h.colind[k] = (int32_t)(pairs[k] % V);
   }
   for (int v = 0; v < V; ++v) h.rowptr[v + 1] += h.rowptr[v];
-  // ---- element lists and gather maps (ascending element order in every list)
-  h.fluid_elems.clear();
-  h.solid_elems.clear();
-  for (int e = 0; e < E; ++e) (h.dom[e] == 0 ? h.fluid_elems : h.solid_elems).push_back(e);
+  // ---- residual gather map (ascending element order in every list)
   h.vinc_ptr.assign(V + 1, 0);
   for (int e = 0; e < E; ++e)
     for (int k = 0; k < 4; ++k) h.vinc_ptr[h.tets[4 * e + k] + 1]++;
@@ -122,8 +119,8 @@ std::string build_topology(HostSetup& h) {
     for (int e = 0; e < E; ++e)
       for (int k = 0; k < 4; ++k) h.vinc[fill[h.tets[4 * e + k]]++] = e * 4 + k;
   }
-  const int64_t nnzb = (int64_t)h.colind.size();
-  std::vector<int32_t> blk((size_t)E * 16);
+  // ---- Jacobian scatter: the block of every (element, local row vertex, local column vertex)
+  h.elem_blk.resize((size_t)E * 16);
   for (int e = 0; e < E; ++e)
     for (int a = 0; a < 4; ++a) {
       int va = h.tets[4 * e + a];
@@ -131,17 +128,51 @@ std::string build_topology(HostSetup& h) {
       const int32_t* c1 = &h.colind[h.rowptr[va + 1]];
       for (int b = 0; b < 4; ++b) {
         const int32_t* p = std::lower_bound(c0, c1, h.tets[4 * e + b]);
-        blk[16 * (size_t)e + 4 * a + b] = (int32_t)(p - h.colind.data());
+        h.elem_blk[16 * (size_t)e + 4 * a + b] = (int32_t)(p - h.colind.data());
       }
     }
-  h.bctr_ptr.assign(nnzb + 1, 0);
-  for (size_t i = 0; i < blk.size(); ++i) h.bctr_ptr[blk[i] + 1]++;
-  for (int64_t k = 0; k < nnzb; ++k) h.bctr_ptr[k + 1] += h.bctr_ptr[k];
-  h.bctr.resize(blk.size());
-  {
-    std::vector<int32_t> fill(h.bctr_ptr.begin(), h.bctr_ptr.end() - 1);
-    for (size_t i = 0; i < blk.size(); ++i) h.bctr[fill[blk[i]]++] = (int32_t)i;  // i = e*16+a*4+b
-  }
+  // ---- element colours, per kind: greedy in ascending element order, the least colour no
+  // element sharing a vertex holds yet.  Elements of one colour touch disjoint block rows
+  // and columns, so one launch per colour adds their element matrices into J without
+  // atomics; colour order fixes the order of the sums.
+  auto colour = [&](int kind, std::vector<int32_t>& elems, std::vector<int32_t>& col) {
+    std::vector<int32_t> ids;
+    for (int e = 0; e < E; ++e)
+      if ((h.dom[e] == 0) == (kind == 0)) ids.push_back(e);
+    int words = 1;
+    std::vector<int32_t> c(ids.size());
+    for (;;) {
+      std::vector<uint64_t> used((size_t)V * words, 0);
+      bool ok = true;
+      for (size_t t = 0; t < ids.size() && ok; ++t) {
+        const int32_t* tv = &h.tets[4 * (size_t)ids[t]];
+        int cc = -1;
+        for (int w = 0; w < words && cc < 0; ++w) {
+          uint64_t u = 0;
+          for (int k = 0; k < 4; ++k) u |= used[(size_t)tv[k] * words + w];
+          if (~u) cc = 64 * w + __builtin_ctzll(~u);
+        }
+        if (cc < 0) { ok = false; break; }
+        c[t] = cc;
+        for (int k = 0; k < 4; ++k) used[(size_t)tv[k] * words + cc / 64] |= uint64_t(1) << (cc % 64);
+      }
+      if (ok) break;
+      words *= 2;
+    }
+    int nc = 0;
+    for (int x : c) nc = std::max(nc, x + 1);
+    col.assign(nc + 1, 0);
+    for (int x : c) col[x + 1]++;
+    for (int k = 0; k < nc; ++k) col[k + 1] += col[k];
+    elems.assign(ids.size(), 0);
+    std::vector<int32_t> fill(col.begin(), col.end() - 1);
+    for (size_t t = 0; t < ids.size(); ++t) elems[fill[c[t]]++] = ids[t];
+  };
+  colour(0, h.fluid_celems, h.fluid_col);
+  colour(1, h.solid_celems, h.solid_col);
+  h.fluid_elems.clear();
+  h.solid_elems.clear();
+  for (int e = 0; e < E; ++e) (h.dom[e] == 0 ? h.fluid_elems : h.solid_elems).push_back(e);
   return "";
 }
 
