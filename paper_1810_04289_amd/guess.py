@@ -40,6 +40,8 @@ CASES = {
     "tube": dict(mesh=lambda: W.tube_mesh(), opts=dict(nsub=4, overlap=1, ilu_level=3)),
     # depth-1 tree, subdomains of the depth-3 benchmark's size
     "tree1": dict(mesh=lambda: W.tree_mesh(depth=1, h=W.TREE_H[1]), opts=dict(nsub=33, overlap=1, ilu_level=3)),
+    # depth-4 tree, ~593k vertices, subdomains of the depth-3 benchmark's size
+    "tree4": dict(mesh=lambda: W.tree_mesh(depth=4, h=W.TREE_H[4]), opts=dict(nsub=768, overlap=1, ilu_level=3)),
 }
 
 

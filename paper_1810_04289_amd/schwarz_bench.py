@@ -1,16 +1,17 @@
 """Batched Schwarz on uneven subdomains: setup, sweeps and GMRES on one MI355X.
 
-Workload: a bifurcating tree (depth 5 by default) cut into subdomains of seeded lognormal
-size (log-standard deviation 0.5, mean about 3,000 vertices), overlap 2, ILU(0), sweeps in
-FP32 from rounded factors under FP64 GMRES.  The Jacobian is the first time step's from
-rest with the wall held rigid (with ILU(0) GMRES stalls on the compliant wall).
+Workload: a bifurcating tree (depth 5 by default: about 1.47M vertices) cut into 512
+subdomains of seeded lognormal size (log-standard deviation 0.5, mean about 2,900
+vertices), overlap 2, ILU(l) (0 by default), sweeps in FP32 from rounded factors under FP64
+GMRES.  The Jacobian is the first time step's from rest with the wall held rigid, or
+(--compliant) the first compliant step's after two rigid-wall steps from rest.
 
 Every subdomain's factorization is one launch (one workgroup per subdomain), and each
 sweep is one launch over all subdomains; the sweep schedule is picked by the library's
 tuner.  Prints one JSON line: subdomain sizes, factorization and sweep times, the sweeps'
 algorithmic bytes and rate, and GMRES iterations and time.
 
-    python -m paper_1810_04289_amd.schwarz_bench [--depth 5] [--h 0.049]
+    python -m paper_1810_04289_amd.schwarz_bench [--depth 5] [--nsub 512] [--ilu 0] [--compliant]
 """
 from __future__ import annotations
 
@@ -32,11 +33,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run(depth=5, h=0.049, mean_size=3000, sigma=0.5, overlap=2, ilu=0, precision=fsi.PREC_FP32, seed=0, reps=20):
+def run(depth=5, h=None, nsub=512, sigma=0.5, overlap=2, ilu=0, precision=fsi.PREC_FP32, seed=0, reps=20,
+        compliant=False):
     import torch
     t0 = time.perf_counter()
-    mesh = W.tree_mesh(depth=depth, h=h)
-    nsub = max(1, round(mesh.nverts / mean_size))
+    mesh = W.tree_mesh(depth=depth, h=W.TREE_H[depth] if h is None else h)
     part = W.uneven_partition(mesh, nsub, sigma=sigma, seed=seed)
     log(f"[schwarz] mesh V={mesh.nverts} E={mesh.ntets}, {nsub} subdomains ({time.perf_counter() - t0:.0f}s)")
     t0 = time.perf_counter()
@@ -44,9 +45,23 @@ def run(depth=5, h=0.049, mean_size=3000, sigma=0.5, overlap=2, ilu=0, precision
                                                    precision=precision, gmres_maxit=600))
     log(f"[schwarz] solver set up ({time.perf_counter() - t0:.0f}s)")
     dt = 1e-3
-    g = s.vec(W.dirichlet_values(mesh, W.inflow_peak(dt)))
-    s.set_step(dt, dt, s.vec(), g, None, W.rigid_wall_mask(mesh))
-    y = s.vec()
+    y_old = s.vec()
+    k0 = 0
+    if compliant:  # two rigid-wall steps from rest, then the first compliant step's Jacobian
+        for k0 in range(2):
+            s.set_step((k0 + 1) * dt, dt, y_old, s.vec(W.dirichlet_values(mesh, W.inflow_peak((k0 + 1) * dt))), None,
+                       W.rigid_wall_mask(mesh))
+            y = y_old.clone()
+            st0, rc = s.newton_solve(y, check=False)
+            log(f"[schwarz] rigid start step {k0}: rc {rc} NI {st0['newton_iters']} "
+                f"LI {st0['lin_hist'][:st0['newton_iters']]}")
+            if rc:
+                raise RuntimeError(f"rigid start step {k0} failed with status {rc}")
+            y_old = y
+        k0 = 2
+    g = s.vec(W.dirichlet_values(mesh, W.inflow_peak((k0 + 1) * dt)))
+    s.set_step((k0 + 1) * dt, dt, y_old, g, None, None if compliant else W.rigid_wall_mask(mesh))
+    y = y_old.clone()
     s.impose_dirichlet(y)
     F = s.vec()
     s.residual(y, F)
@@ -84,7 +99,9 @@ def run(depth=5, h=0.049, mean_size=3000, sigma=0.5, overlap=2, ilu=0, precision
     ext = np.diff(pc["sub_ptr"])
     out = {"workload": f"tree depth {depth}, {mesh.nverts} vertices, {s.n} unknowns, {nsub} uneven subdomains "
                        f"(lognormal sigma {sigma}, mean {mesh.nverts / nsub:.0f} vertices), overlap {overlap}, "
-                       f"ILU({ilu}), sweeps {['FP64', 'FP32', 'BF16 factors'][precision]}, rigid wall, first step",
+                       f"ILU({ilu}), sweeps {['FP64', 'FP32', 'BF16 factors'][precision]}, "
+                       + ("compliant wall, first compliant step after two rigid ones" if compliant
+                          else "rigid wall, first step"),
            "owned": {"min": int(owned.min()), "mean": float(owned.mean()), "max": int(owned.max())},
            "extended": {"min": int(ext.min()), "mean": float(ext.mean()), "max": int(ext.max())},
            "local_blocks": sw["local_blocks"], "pc_setup_ms": round(1e3 * t_setup, 2),
@@ -103,14 +120,15 @@ def run(depth=5, h=0.049, mean_size=3000, sigma=0.5, overlap=2, ilu=0, precision
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--depth", type=int, default=5)
-    ap.add_argument("--h", type=float, default=0.049)
-    ap.add_argument("--mean-size", type=int, default=3000)
+    ap.add_argument("--h", type=float, default=None, help="lattice spacing (default: the depth's workload spacing)")
+    ap.add_argument("--nsub", type=int, default=512)
+    ap.add_argument("--compliant", action="store_true")
     ap.add_argument("--ilu", type=int, default=0)
     ap.add_argument("--overlap", type=int, default=2)
     ap.add_argument("--precision", type=int, default=fsi.PREC_FP32)
     a = ap.parse_args()
-    print(json.dumps(run(depth=a.depth, h=a.h, mean_size=a.mean_size, overlap=a.overlap, ilu=a.ilu,
-                         precision=a.precision)), flush=True)
+    print(json.dumps(run(depth=a.depth, h=a.h, nsub=a.nsub, overlap=a.overlap, ilu=a.ilu,
+                         precision=a.precision, compliant=a.compliant)), flush=True)
 
 
 if __name__ == "__main__":

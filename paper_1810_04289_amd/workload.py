@@ -32,8 +32,9 @@ FLUID = 0
 SOLID = 1
 
 # Lattice spacing (cm) of the tree workloads: depth 3 gives about 203k vertices and
-# 1.37M active unknowns; depth 1 (about 26k vertices) is the small sampled variant.
-TREE_H = {1: 0.08, 3: 0.049}
+# 1.37M active unknowns; depth 1 (about 26k vertices) is the small sampled variant; depths
+# 4, 5 and 6 give about 593k, 1.47M and 3.84M vertices.
+TREE_H = {1: 0.08, 3: 0.049, 4: 0.036, 5: 0.0278, 6: 0.0209}
 
 # Faces of a positively oriented tet (v0..v3), each listed with outward orientation.
 _TET_FACES = np.array([[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]], dtype=np.int64)
@@ -109,9 +110,24 @@ def _min_edge_length(X: np.ndarray, tets: np.ndarray) -> np.ndarray:
 
 def _compact(X, tets):
     used = np.unique(tets)
-    remap = -np.ones(X.shape[0], dtype=np.int64)
-    remap[used] = np.arange(len(used))
-    return X[used], remap[tets], used
+    return X[used], np.searchsorted(used, tets), used
+
+
+def _rows_in(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Mask of the rows of A (int [n,3]) that also occur as rows of B."""
+    if len(A) == 0 or len(B) == 0:
+        return np.zeros(len(A), dtype=bool)
+    allr = np.concatenate([B, A]).astype(np.int64)
+    fromA = np.r_[np.zeros(len(B), dtype=bool), np.ones(len(A), dtype=bool)]
+    order = np.lexsort((allr[:, 2], allr[:, 1], allr[:, 0]))
+    srt = allr[order]
+    new = np.r_[True, np.any(srt[1:] != srt[:-1], axis=1)]
+    gid = np.cumsum(new) - 1
+    hasB = np.zeros(int(gid[-1]) + 1, dtype=bool)
+    hasB[gid[~fromA[order]]] = True
+    out = np.empty(len(A), dtype=bool)
+    out[order[fromA[order]] - len(B)] = hasB[gid[fromA[order]]]
+    return out
 
 
 # ----------------------------------------------------------------------------------------
@@ -367,11 +383,24 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
         return np.stack([i, j, k], -1) * h + lo
 
     cen = (lat_xyz(T[:, 0]) + lat_xyz(T[:, 1]) + lat_xyz(T[:, 2]) + lat_xyz(T[:, 3])) / 4.0
-    sdf = np.full(len(T), np.inf)
+    # Each branch is evaluated only on the tets of candidate cells inside its bounding box
+    # (of the extended axis for a terminal branch), padded by r + margin + 2h: a tet farther
+    # away can be neither inside the branch (radial < r) nor in its void (radial < r + margin).
+    neg = np.zeros(len(T), dtype=bool)    # some branch puts the centroid inside the lumen
     void = np.zeros(len(T), dtype=bool)
     planes = []  # (axis, lattice index) of each outlet plane
+
+    def near(P0, P1, pad):
+        blo = np.floor((np.minimum(P0, P1) - pad - lo) / h).astype(int)
+        bhi = np.ceil((np.maximum(P0, P1) + pad - lo) / h).astype(int)
+        blo = np.clip(blo, 0, [nx - 1, ny - 1, nz - 1])
+        bhi = np.clip(bhi, 0, [nx - 1, ny - 1, nz - 1])
+        sel = ((ci >= blo[0]) & (ci <= bhi[0]) & (cj >= blo[1]) & (cj <= bhi[1]) & (ck >= blo[2]) & (ck <= bhi[2]))
+        pos = np.nonzero(sel)[0]
+        return (6 * pos[:, None] + np.arange(6)[None]).ravel()
+
     for b in br:
-        t, d = _seg_param(cen, b.A, b.B)
+        d = b.B - b.A
         L = np.linalg.norm(d)
         if b.terminal:
             # The outlet is the lattice plane nearest the branch end, normal to the lattice
@@ -385,15 +414,22 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
             planes.append((ax, kp))
             ext = (b.r + margin) * math.sqrt(max(1.0 - dn[ax] ** 2, 0.0)) / abs(dn[ax]) + 2 * h
             tmax = 1.0 + ext / L
+            idx = near(b.A, b.A + tmax * d, b.r + margin + 2 * h)
+            c = cen[idx]
+            t, _ = _seg_param(c, b.A, b.B)
             tc = np.clip(t, 0.0, tmax)
-            radial = np.linalg.norm(cen - (b.A[None] + tc[:, None] * d[None]), axis=1)
-            beyond = sg * (cen[:, ax] - cpl) > 0
-            void |= beyond & (t > 0.5) & (radial < b.r + margin)
-            ds = np.where(beyond & (t > 0.5), np.inf, radial - b.r)
+            radial = np.linalg.norm(c - (b.A[None] + tc[:, None] * d[None]), axis=1)
+            beyond = sg * (c[:, ax] - cpl) > 0
+            void[idx] |= beyond & (t > 0.5) & (radial < b.r + margin)
+            inside = ~(beyond & (t > 0.5)) & (radial - b.r < 0)
         else:
+            idx = near(b.A, b.B, b.r + margin + 2 * h)
+            c = cen[idx]
+            t, _ = _seg_param(c, b.A, b.B)
             tc = np.clip(t, 0.0, 1.0)
-            ds = np.linalg.norm(cen - (b.A[None] + tc[:, None] * d[None]), axis=1) - b.r
-        sdf = np.minimum(sdf, ds)
+            inside = np.linalg.norm(c - (b.A[None] + tc[:, None] * d[None]), axis=1) - b.r < 0
+        neg[idx] |= inside
+    sdf = np.where(neg, -1.0, 1.0)
     fluid = (sdf < 0) & ~void
     fv = np.zeros(int(n1.prod()), dtype=bool)
     fv[T[fluid].ravel()] = True
@@ -406,16 +442,14 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
     Tv = T[void & ~keep]
 
     # faces of mesh tets that border void tets, or lie on the top (inlet) plane
-    vkey = np.sort(Tv[:, _TET_FACES].reshape(-1, 3), axis=1)
-    vset = set(map(tuple, vkey.tolist()))
+    vkey = np.unique(np.sort(Tv[:, _TET_FACES].reshape(-1, 3), axis=1), axis=0)
 
-    Xl = lat_xyz(np.arange(int(n1.prod())))
-    X, tets, used = _compact(Xl, Tm)
+    used = np.unique(Tm)
+    X, tets = lat_xyz(used), np.searchsorted(used, Tm)
     ktop = (used // (n1[0] * n1[1])) == nz
     lidx = np.stack([used % n1[0], (used // n1[0]) % n1[1], used // (n1[0] * n1[1])], 1)
     # vertices of outlet caps (faces shared with void tets) stay in their plane
-    vkeys = np.array(sorted(vset), dtype=np.int64).reshape(-1, 3) if vset else np.zeros((0, 3), np.int64)
-    on_cap = np.isin(used, np.unique(vkeys))
+    on_cap = np.isin(used, np.unique(vkey))
 
     # seeded jitter (5% of h); inlet-plane and outlet-plane vertices move in-plane only
     rng = np.random.default_rng(seed + 1)
@@ -430,7 +464,7 @@ def tree_mesh(depth: int = 3, h: float = 0.046, seed: int = 0, jitter: float = 0
     bdom = dom[owner]
     glob = used[bf]
     gkey = np.sort(glob, axis=1)
-    on_void = np.array([tuple(k) in vset for k in gkey.tolist()], dtype=bool)
+    on_void = _rows_in(gkey, vkey)
     on_top = np.all(ktop[bf], axis=1)
     tag = np.zeros(len(bf), dtype=np.int8)
     tag[(bdom == FLUID) & on_top] = TAG_FLUID_INLET
