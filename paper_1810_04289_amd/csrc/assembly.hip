@@ -407,18 +407,19 @@ __global__ void __launch_bounds__(256) k_jac_init(int64_t nnzb, const int32_t* _
                                                   const int32_t* __restrict__ colind,
                                                   const uint8_t* __restrict__ rowkind, double dt,
                                                   double* __restrict__ vals) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nnzb * 49) return;
-  const int64_t k = gid / 49;
-  const int ent = (int)(gid % 49), r = ent / 7, c = ent % 7;
-  const int a = blkrow[k];
-  const uint8_t kind = rowkind[7 * (size_t)a + r];
-  double out = 0.0;
-  if (kind != RK_ELEM && colind[k] == a) {
-    if (kind == RK_KIN) out = (c == r) ? 1.0 : (c == r - 4 ? -dt : 0.0);
-    else out = (c == r) ? 1.0 : 0.0;
+  const int64_t n = nnzb * 49, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
+    const int64_t k = gid / 49;
+    const int ent = (int)(gid - 49 * k), r = ent / 7, c = ent % 7;
+    const int a = blkrow[k];
+    const uint8_t kind = rowkind[7 * (size_t)a + r];
+    double out = 0.0;
+    if (kind != RK_ELEM && colind[k] == a) {
+      if (kind == RK_KIN) out = (c == r) ? 1.0 : (c == r - 4 ? -dt : 0.0);
+      else out = (c == r) ? 1.0 : 0.0;
+    }
+    vals[gid] = out;
   }
-  vals[gid] = out;
 }
 
 __global__ void k_impose(int64_t n, const uint8_t* __restrict__ rowkind, const double* __restrict__ gval,
@@ -431,6 +432,12 @@ __global__ void k_impose(int64_t n, const uint8_t* __restrict__ rowkind, const d
 }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// Per-entry launches (49 per block) stride over a capped grid: a dispatch packet holds the
+// grid size as a 32-bit count of work-items.
+static inline unsigned nblk_stride(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < (int64_t(1) << 20) ? (b > 0 ? b : 1) : (int64_t(1) << 20));
+}
 
 hipError_t launch_impose(fsi_solver* s, double* y) {
   if (s->n == 0) return hipSuccess;
@@ -460,7 +467,7 @@ hipError_t launch_jacobian(fsi_solver* s, const double* y) {
   const PhysDev P = phys_dev(s);
   const double* bf = s->has_bforce ? s->bforce : nullptr;
   FSI_PROF_LAUNCH(s, "jac_init",
-                  hipLaunchKernelGGL(k_jac_init, dim3(nblk(s->nnzb * 49, 256)), dim3(256), 0, s->stream, s->nnzb,
+                  hipLaunchKernelGGL(k_jac_init, dim3(nblk_stride(s->nnzb * 49)), dim3(256), 0, s->stream, s->nnzb,
                                      s->blkrow, s->colind, s->rowkind, s->dt, s->vals));
   // one launch per colour, fluid colours then wall colours
   const std::vector<int32_t>& fc = s->h.fluid_col;

@@ -96,7 +96,7 @@ double norm2(fsi_solver* s, const double* a) {
 }
 
 void clear_flags(fsi_solver* s) {
-  hip_ok(s, hipMemsetAsync(s->flags, 0, 4 * sizeof(int32_t), s->stream), "memset flags");
+  hip_ok(s, hipMemsetAsync(s->flags, 0, kFlags * sizeof(int32_t), s->stream), "memset flags");
 }
 
 // the sweeps' flag alone, before the calls that report it (so that an earlier call's
@@ -107,15 +107,15 @@ void clear_sweep_flag(fsi_solver* s) {
 
 // the four device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound,
 // [3] sweep wait bound
-void read_flags(fsi_solver* s, int32_t out[4]) {
-  hip_ok(s, hipMemcpyAsync(&s->pinned[200], s->flags, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
+void read_flags(fsi_solver* s, int32_t out[kFlags]) {
+  hip_ok(s, hipMemcpyAsync(&s->pinned[200], s->flags, kFlags * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream),
          "flag readback");
   sync(s);
-  std::memcpy(out, &s->pinned[200], 4 * sizeof(int32_t));
+  std::memcpy(out, &s->pinned[200], kFlags * sizeof(int32_t));
 }
 
 int32_t read_flag(fsi_solver* s, int which) {
-  int32_t v[4];
+  int32_t v[kFlags];
   read_flags(s, v);
   return v[which];
 }
@@ -151,14 +151,23 @@ fsi_status pc_setup_impl(fsi_solver* s) {
   clear_flags(s);
   hip_ok(s, launch_pc_setup(s), "pc_setup");
   hip_ok(s, launch_fac_round(s), "factor rounding");
-  int32_t f[4];
+  int32_t f[kFlags];
   read_flags(s, f);
   if (f[2]) {
     s->err = "a subdomain factorization waited on a pivot row beyond its bound";
     return FSI_ERR_HIP;
   }
   if (f[1]) {
-    s->err = "zero pivot in a subdomain factorization";
+    // the first and the last local row whose pivot block was singular, and their number
+    const auto& off = s->h.sub_row_off;
+    auto where = [&](int64_t r) {
+      const int64_t sd = (int64_t)(std::upper_bound(off.begin(), off.end(), (int32_t)r) - off.begin()) - 1;
+      if (r < 0 || sd < 0 || r >= (int64_t)s->h.lglob.size()) return std::string("?");
+      return "subdomain " + std::to_string(sd) + ", local row " + std::to_string(r - off[sd]) + " (vertex " +
+             std::to_string(s->h.lglob[r]) + ")";
+    };
+    s->err = "zero pivot in a subdomain factorization: " + std::to_string(f[6]) + " singular pivot blocks, first at " +
+             where(0x7fffffff - (int64_t)f[5]) + ", last at " + where((int64_t)f[4] - 1);
     return FSI_ERR_ZERO_PIVOT;
   }
   s->pc_ready = true;
@@ -606,6 +615,7 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->fw_lvl = upload(s, wlvl);
   }
   s->umap = upload(s, h.umap);
+  s->umap_row = upload(s, h.umap_row);
   s->sub_row_off = upload(s, h.sub_row_off);
   s->fac = dalloc<double>(s, (size_t)s->NB * 49);
   if (s->opts.precision == FSI_PREC_FP32) s->facs = dalloc<float>(s, (size_t)s->NB * 49);
@@ -626,10 +636,10 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->yt = dalloc<double>(s, s->n);
   s->dy = dalloc<double>(s, s->n);
   s->rhs = dalloc<double>(s, s->n);
-  s->flags = dalloc<int32_t>(s, 4);
+  s->flags = dalloc<int32_t>(s, kFlags);
   hip_ok(s, hipHostMalloc((void**)&s->pinned, 4 * (kMaxRestart + 8) * sizeof(double), hipHostMallocDefault),
          "hipHostMalloc");
-  hip_ok(s, hipMemset(s->flags, 0, 4 * sizeof(int32_t)), "memset");
+  hip_ok(s, hipMemset(s->flags, 0, kFlags * sizeof(int32_t)), "memset");
   hip_ok(s, hipMemset(s->hdev, 0, 4 * (kMaxRestart + 8) * sizeof(double)), "memset");
   hip_ok(s, hipDeviceSynchronize(), "sync");
   scratch_attach(s);

@@ -18,6 +18,10 @@ enum : uint8_t { RK_ELEM = 0, RK_DIR = 1, RK_KIN = 2, RK_DUMMY = 3 };
 constexpr int kMaxRestart = 200;
 constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic sums
 constexpr int kSweepWaves = 8;    // wavefronts per subdomain in the triangular sweeps
+// device flags: [0] inverted element, [1] zero pivot, [2] factorization wait bound, [3] sweep
+// wait bound, [4] 1 + the last local row with a singular pivot block, [5] INT32_MAX - the
+// first such row, [6] how many there are
+constexpr int kFlags = 8;
 constexpr int kFacHalf = 9;      // factorization group: 2 * kFacHalf U blocks, lane q < 63 takes two
 
 // Host-side setup products (independent of any device state).
@@ -57,11 +61,13 @@ struct HostSetup {
   std::vector<int32_t> fwd_sub_lvl, fwd_lvl_ptr, fwd_rows;
   std::vector<int32_t> bwd_sub_lvl, bwd_lvl_ptr, bwd_rows;
   // factorization work lists: row i's pivots are piv[4*kent_ptr[i] .. 4*kent_ptr[i+1]),
-  // each {position of A_ik in row i, D_k block, length n of U_k, offset o into umap};
-  // umap[o + t] = 1 + position in row i of the block matching U_k's t-th block, or 0
+  // each {position of A_ik in row i, D_k block, length n of U_k, offset o into row i's
+  // part of umap}; umap[umap_row[i] + o + t] = 1 + position in row i of the block matching
+  // U_k's t-th block, or 0.  (The whole map can exceed 2^31 entries; a row's part cannot.)
   std::vector<int32_t> kent_ptr;  // [R+1]
   std::vector<int32_t> piv;       // [4K]
   std::vector<int32_t> umap;      // [sum of the pivots' U lengths]
+  std::vector<int64_t> umap_row;  // [R+1] start of each row's part of umap
   // LDS slots of the sweeps: a row's result occupies a slot from its level to the level
   // of its last reader (interval colouring per subdomain and direction).
   std::vector<int32_t> fwd_qslot, bwd_qslot;  // per schedule slot: own LDS slot or -1 (no reader)
@@ -149,6 +155,7 @@ struct fsi_solver {
   // (ascending) U_k in runs of up to 2*kFacHalf blocks (one run if U_k is empty):
   // {first U block, D_k block, map offset, (position of A_ik << 6) | (blocks << 1) | first run}
   int32_t *fgrp_ptr = nullptr, *umap = nullptr;
+  int64_t* umap_row = nullptr;
   int4* fgrp = nullptr;
   // fgrp_lvl[g]: forward level of group g's pivot row.  The factorization's rows go to its
   // fac_nw wavefronts round-robin in level order: wavefront w of subdomain s factors rows

@@ -26,15 +26,23 @@
 namespace fsi {
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// A dispatch packet holds the grid size as a 32-bit count of work-items, so launches over
+// per-entry ranges (49 per block, past 2^32 at the largest subdomain sets) stride over a
+// capped grid instead of launching one work-item per entry.
+static inline unsigned nblk_stride(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b < (int64_t(1) << 20) ? (b > 0 ? b : 1) : (int64_t(1) << 20));
+}
 
 __global__ void __launch_bounds__(256) k_ilu_gather(int64_t nb, const int32_t* __restrict__ lsrc,
                                                     const double* __restrict__ vals, double* __restrict__ fac) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= nb * 49) return;
-  const int64_t p = gid / 49;
-  const int e = (int)(gid % 49);
-  const int src = lsrc[p];
-  fac[gid] = src >= 0 ? vals[49 * (size_t)src + e] : 0.0;
+  const int64_t n = nb * 49, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
+    const int64_t p = gid / 49;
+    const int e = (int)(gid - 49 * p);
+    const int src = lsrc[p];
+    fac[gid] = src >= 0 ? vals[49 * (size_t)src + e] : 0.0;
+  }
 }
 
 // Wavefront-scope ordering of LDS accesses between lanes of one wavefront (LDS operations
@@ -145,6 +153,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int4* __restrict__ fgrp,
                                                    const int32_t* __restrict__ fgrp_lvl,
                                                    const int32_t* __restrict__ umap,
+                                                   const int64_t* __restrict__ umap_row,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int slice, int wait_limit) {
@@ -205,6 +214,10 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     double* grow = fac + gb;  // the row in memory
     // the row's blocks past the slice are read and written through buffer instructions
     const __amdgpu_buffer_rsrc_t rrow = span_rsrc(grow, 8 * nbe);
+    // this row's part of the U-position map (uniform: kept in scalar registers)
+    const int64_t ub = umap_row[i];
+    const int32_t* urow = umap + (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ub)) |
+                                           ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(ub >> 32)) << 32));
     const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
     const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
     // c0 holds groups [cb, cb + 64) (descriptors, and pivot levels in v0) and c1 / v1 the
@@ -287,7 +300,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       for (int k = 0; k + 1 < P; ++k) {
         const int u = k < ng ? k : ng - 1;
         wait_final(__builtin_amdgcn_readlane(v0, u - cb));  // pivot row final before its blocks are read
-        fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, umap, voff_u, voff_d, lane);
+        fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, urow, voff_u, voff_d, lane);
       }
       for (int t0 = 0; t0 < ng; t0 += P) {
 #pragma unroll
@@ -302,7 +315,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
           }
           const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
           wait_final(__builtin_amdgcn_readlane(v0, u - cb));
-          fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, umap, voff_u, voff_d,
+          fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, urow, voff_u, voff_d,
                          lane);
           if (t < ng) consume(buf[k], desc_get(c0, t - cb));
         }
@@ -357,7 +370,12 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     // entry (rr, cc) of A^{-1} is c_rr Ah^{-1}(rr, cc) r_cc: c_rr from lane (0, rr), r_cc
     // from lane (cc, 0)
     Iv = __shfl(cs, rr, 64) * Iv * __shfl(rs, 7 * cc, 64);
-    if (bad && lane == 0) atomicOr(&flags[1], 1);
+    if (bad && lane == 0) {
+      atomicOr(&flags[1], 1);
+      atomicMax(&flags[4], i + 1);  // i: the concatenated local row
+      atomicMax(&flags[5], 0x7fffffff - i);
+      atomicAdd(&flags[6], 1);
+    }
     wave_lds_sync();
     if (owner) {
       if (pdb < slice) row[pdb * 49 + ent] = Iv;
@@ -405,7 +423,7 @@ FacLayout fac_layout(int max_rowblk) {
 
 hipError_t launch_pc_setup(fsi_solver* s) {
   if (s->NB == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ilu_gather, dim3(nblk(s->NB * 49, 256)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
+  hipLaunchKernelGGL(k_ilu_gather, dim3(nblk_stride(s->NB * 49)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
                      s->fac);
   // up to four row-staging wavefronts per workgroup, as many as the longest row allows (the
   // rows were dealt to that many wavefronts at create)
@@ -420,6 +438,7 @@ hipError_t launch_pc_setup(fsi_solver* s) {
     FSI_PROF_LAUNCH(s, "ilu_factor",
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
                                        s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
+                                       s->umap_row,
                                        s->ldiag, s->fac, s->udiag, s->flags, fl.slice, s->wait_limit));
     return hipSuccess;
   };
@@ -772,26 +791,27 @@ size_t pc_apply_ws_bytes(const fsi_solver* s) {
 
 // Sweep copy of the factors: FP64 rounded to nearest FP32, or to nearest-even BF16.
 __global__ void __launch_bounds__(256) k_fac_round_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
 }
 __global__ void __launch_bounds__(256) k_fac_round_bf16(int64_t n, const double* __restrict__ a,
                                                         uint16_t* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t u = __float_as_uint((float)a[i]);
-  // round to nearest even on the 16 dropped bits; NaN stays NaN
-  const uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
-  b[i] = (uint16_t)(r >> 16);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t u = __float_as_uint((float)a[i]);
+    // round to nearest even on the 16 dropped bits; NaN stays NaN
+    const uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+    b[i] = (uint16_t)(r >> 16);
+  }
 }
 
 hipError_t launch_fac_round(fsi_solver* s) {
   const int64_t n = s->NB * 49;
   if (n == 0 || s->opts.precision == FSI_PREC_FP64) return hipSuccess;
   if (s->opts.precision == FSI_PREC_FP32)
-    hipLaunchKernelGGL(k_fac_round_f32, dim3(nblk(n, 256)), dim3(256), 0, s->stream, n, s->fac, (float*)s->facs);
+    hipLaunchKernelGGL(k_fac_round_f32, dim3(nblk_stride(n)), dim3(256), 0, s->stream, n, s->fac, (float*)s->facs);
   else
-    hipLaunchKernelGGL(k_fac_round_bf16, dim3(nblk(n, 256)), dim3(256), 0, s->stream, n, s->fac,
+    hipLaunchKernelGGL(k_fac_round_bf16, dim3(nblk_stride(n)), dim3(256), 0, s->stream, n, s->fac,
                        (uint16_t*)s->facs);
   return hipGetLastError();
 }

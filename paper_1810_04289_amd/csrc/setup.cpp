@@ -408,6 +408,7 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
   h.kent_ptr.assign(1, 0);
   h.piv.clear();
   h.umap.clear();
+  h.umap_row.assign(1, 0);
 
   std::vector<int32_t> owners_of(V);
   std::vector<std::vector<int32_t>> members(ns);
@@ -535,7 +536,8 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
       for (int p = rowb(i); p < h.ldiag[base + i]; ++p) {
         const int k = h.lcol[p] - base;
         const int u0 = h.ldiag[base + k] + 1, u1 = rowe(k);
-        h.piv.insert(h.piv.end(), {p - rowb(i), h.ldiag[base + k], u1 - u0, (int32_t)h.umap.size()});
+        h.piv.insert(h.piv.end(), {p - rowb(i), h.ldiag[base + k], u1 - u0,
+                                   (int32_t)((int64_t)h.umap.size() - h.umap_row.back())});
         const int32_t* f = ci0;
         for (int q = u0; q < u1; ++q) {  // both column lists ascend: one merge walk
           f = std::lower_bound(f, ci1, h.lcol[q]);
@@ -543,6 +545,7 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
         }
       }
       h.kent_ptr.push_back((int32_t)(h.piv.size() / 4));
+      h.umap_row.push_back((int64_t)h.umap.size());
     }
     // LDS slots for the sweeps: y_k (forward) or x_k (backward) is live from its own level
     // to the level of its last reader; slots are handed out greedily in level order and

@@ -530,6 +530,53 @@ def tree(fsi_mod):
     return m
 
 
+def lu_identity_worst(pc, rp, ci, Vg, s, rng, nrows):
+    """Largest entry of |LU - A| / (|L||U|) over `nrows` sampled rows of subdomain s, on the
+    subdomain's factor pattern, with A the assembled matrix restricted to the subdomain."""
+    v0, v1 = pc["sub_ptr"][s], pc["sub_ptr"][s + 1]
+    b0 = pc["blk_ptr"][s]
+    lrp = pc["lrowptr"][v0 + s:v1 + s + 1]
+    lci = pc["lcolind"][b0:pc["blk_ptr"][s + 1]]
+    f = pc["factors"][b0:pc["blk_ptr"][s + 1]]
+    ud = pc["udiag"][v0:v1]
+    verts = pc["sub_verts"][v0:v1]
+    mm = len(verts)
+    pos = {int(v): i for i, v in enumerate(verts)}
+
+    def Lblk(i, k):
+        if i == k:
+            return np.eye(7)
+        r = lrp[i] + np.searchsorted(lci[lrp[i]:lrp[i + 1]], k)
+        return f[r] if r < lrp[i + 1] and lci[r] == k else None
+
+    def Ublk(k, j):
+        if k == j:
+            return ud[k]
+        r = lrp[k] + np.searchsorted(lci[lrp[k]:lrp[k + 1]], j)
+        return f[r] if r < lrp[k + 1] and lci[r] == j else None
+
+    worst = 0.0
+    for i in rng.choice(mm, min(nrows, mm), replace=False):
+        a = int(verts[i])
+        Arow = {pos[int(c)]: Vg[rp[a] + kk] for kk, c in enumerate(ci[rp[a]:rp[a + 1]]) if int(c) in pos}
+        errs, scales = [], np.zeros(7)
+        for j in lci[lrp[i]:lrp[i + 1]]:
+            acc = np.zeros((7, 7))
+            aacc = np.zeros((7, 7))
+            for k in lci[lrp[i]:lrp[i + 1]]:
+                if k > min(i, j):
+                    continue
+                Lb, Ub = Lblk(i, k), Ublk(k, j)
+                if Lb is not None and Ub is not None:
+                    acc += Lb @ Ub
+                    aacc += np.abs(Lb) @ np.abs(Ub)
+            Aij = Arow.get(int(j), np.zeros((7, 7)))
+            errs.append(np.abs(acc - Aij).max(1))
+            scales = np.maximum(scales, aacc.max(1))
+        worst = max(worst, float((np.max(errs, axis=0) / scales).max()))
+    return worst
+
+
 def test_full_size_residual_parity(tree, fsi_mod):
     m = tree
     g = W.dirichlet_values(m, 30.0)
@@ -565,51 +612,38 @@ def test_full_size_residual_parity(tree, fsi_mod):
         assert rowrel(G, R) <= 1e-12
     # factorization identity LU = A on sampled rows of one subdomain, with GPU factors
     P.g.pc_setup()
-    pc = P.g.pc_get()
     s = 137
-    v0, v1 = pc["sub_ptr"][s], pc["sub_ptr"][s + 1]
-    b0 = pc["blk_ptr"][s]
-    lrp = pc["lrowptr"][v0 + s:v1 + s + 1]
-    lci = pc["lcolind"][b0:pc["blk_ptr"][s + 1]]
-    f = pc["factors"][b0:pc["blk_ptr"][s + 1]]
-    ud = pc["udiag"][v0:v1]
-    verts = pc["sub_verts"][v0:v1]
-    mm = len(verts)
-    pos = {int(v): i for i, v in enumerate(verts)}
-
-    def Lblk(i, k):
-        if i == k:
-            return np.eye(7)
-        r = lrp[i] + np.searchsorted(lci[lrp[i]:lrp[i + 1]], k)
-        return f[r] if r < lrp[i + 1] and lci[r] == k else None
-
-    def Ublk(k, j):
-        if k == j:
-            return ud[k]
-        r = lrp[k] + np.searchsorted(lci[lrp[k]:lrp[k + 1]], j)
-        return f[r] if r < lrp[k + 1] and lci[r] == j else None
-
-    worst = 0.0
-    for i in rng.choice(mm, 12, replace=False):
-        a = int(verts[i])
-        Arow = {pos[int(c)]: Vg[rp[a] + kk] for kk, c in enumerate(ci[rp[a]:rp[a + 1]]) if int(c) in pos}
-        errs, scales = [], np.zeros(7)
-        for j in lci[lrp[i]:lrp[i + 1]]:
-            acc = np.zeros((7, 7))
-            aacc = np.zeros((7, 7))
-            for k in lci[lrp[i]:lrp[i + 1]]:
-                if k > min(i, j):
-                    continue
-                Lb, Ub = Lblk(i, k), Ublk(k, j)
-                if Lb is not None and Ub is not None:
-                    acc += Lb @ Ub
-                    aacc += np.abs(Lb) @ np.abs(Ub)
-            Aij = Arow.get(int(j), np.zeros((7, 7)))
-            errs.append(np.abs(acc - Aij).max(1))
-            scales = np.maximum(scales, aacc.max(1))
-        worst = max(worst, float((np.max(errs, axis=0) / scales).max()))
+    worst = lu_identity_worst(P.g.pc_get(), rp, ci, Vg, s, rng, 12)
     say(f"  full-size LU=A on pattern (subdomain {s}), relative to |L||U|: {worst:.3e}")
     assert worst <= 1e-12
+
+
+def test_factor_storage_past_2_32_entries(fsi_mod):
+    # Depth-4 tree, 768 subdomains, overlap 2, ILU(3): the local factor pattern holds about
+    # 9.6e7 blocks, so 4.7e9 doubles, past the 2^32 work-items one dispatch can count. The
+    # last subdomain's factor entries all lie beyond entry 2^32; LU = A on its rows shows
+    # that they were gathered and factored.
+    m = W.tree_mesh(depth=4, h=W.TREE_H[4])
+    say(f"[tree4] V={m.nverts} E={m.ntets}")
+    s = fsi_mod.Solver(m, W.physics_config1(), dict(nsub=768, overlap=2, ilu_level=3))
+    try:
+        dt = 1e-3
+        s.set_step(dt, dt, s.vec(), s.vec(W.dirichlet_values(m, W.inflow_peak(dt))), None, W.rigid_wall_mask(m))
+        y = s.vec()
+        s.impose_dirichlet(y)
+        s.jacobian(y)
+        s.pc_setup()
+        rp, ci, Vg = s.jacobian_get()
+        pc = s.pc_get()
+        nb = len(pc["lcolind"])
+        last = len(pc["sub_ptr"]) - 2
+        say(f"  local blocks {nb}, entries {49 * nb}, last subdomain starts at entry {49 * pc['blk_ptr'][last]}")
+        assert 49 * int(pc["blk_ptr"][last]) > 2 ** 32
+        worst = lu_identity_worst(pc, rp, ci, Vg, last, np.random.default_rng(3), 16)
+        say(f"  LU=A on the last subdomain, relative to |L||U|: {worst:.3e}")
+        assert worst <= 1e-12
+    finally:
+        s.close()
 
 
 @pytest.mark.parametrize("rigid,ordering", [(True, 0), (False, 0), (False, 1)])
