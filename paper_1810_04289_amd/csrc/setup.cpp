@@ -3,49 +3,85 @@
 // reverse Cuthill-McKee, the ILU(l) fill pattern, level schedules and the factorization
 // work lists.  All of it runs once per mesh; the products are uploaded to HBM.
 #include <algorithm>
+#include <atomic>
 #include <climits>
+#include <condition_variable>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <numeric>
 #include <queue>
+#include <thread>
 
 #include "fsi_internal.hpp"
 
 namespace fsi {
+
+// Host threads of the set-up: every threaded step computes per-item results that do not
+// depend on the thread count, so the products are the same for any count.
+static int setup_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hw, 16u));
+}
+
+// f(begin, end) over [0, n) in one contiguous range per thread
+template <class F>
+static void parallel_ranges(int64_t n, F&& f) {
+  const int T = setup_threads();
+  if (T <= 1 || n < 4096) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+  for (auto& x : th) x.join();
+}
 
 // Outward faces of a positively oriented tetrahedron.
 static const int kTetFace[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
 
 std::string build_topology(HostSetup& h) {
   const int V = h.V, E = h.E;
-  // ---- Algorithm 1 (§4.8): interface triangles.  Faces are matched by sorting the
-  // sorted vertex triples; a fluid face whose twin belongs to a wall element is an
-  // interface triangle.
-  struct Rec { int32_t a, b, c, e, f; };
-  std::vector<Rec> rec((size_t)E * 4);
+  // ---- vertex -> (e*4 + local) in ascending element order; the residual's gather map, and
+  // the incidence lists the steps below search
+  h.vinc_ptr.assign(V + 1, 0);
   for (int e = 0; e < E; ++e)
-    for (int f = 0; f < 4; ++f) {
-      int32_t v[3] = {h.tets[4 * e + kTetFace[f][0]], h.tets[4 * e + kTetFace[f][1]],
-                      h.tets[4 * e + kTetFace[f][2]]};
-      std::sort(v, v + 3);
-      rec[4 * (size_t)e + f] = {v[0], v[1], v[2], e, f};
-    }
-  std::sort(rec.begin(), rec.end(), [](const Rec& x, const Rec& y) {
-    if (x.a != y.a) return x.a < y.a;
-    if (x.b != y.b) return x.b < y.b;
-    if (x.c != y.c) return x.c < y.c;
-    return x.e < y.e;
-  });
-  std::vector<int32_t> twin((size_t)E * 4, -1);  // element across each face
-  for (size_t i = 0; i < rec.size();) {
-    size_t j = i + 1;
-    while (j < rec.size() && rec[j].a == rec[i].a && rec[j].b == rec[i].b && rec[j].c == rec[i].c) ++j;
-    if (j - i > 2) return "a face is shared by more than two elements";
-    if (j - i == 2) {
-      twin[4 * (size_t)rec[i].e + rec[i].f] = rec[i + 1].e;
-      twin[4 * (size_t)rec[i + 1].e + rec[i + 1].f] = rec[i].e;
-    }
-    i = j;
+    for (int k = 0; k < 4; ++k) h.vinc_ptr[h.tets[4 * (size_t)e + k] + 1]++;
+  for (int v = 0; v < V; ++v) h.vinc_ptr[v + 1] += h.vinc_ptr[v];
+  h.vinc.resize((size_t)E * 4);
+  {
+    std::vector<int32_t> fill(h.vinc_ptr.begin(), h.vinc_ptr.end() - 1);
+    for (int e = 0; e < E; ++e)
+      for (int k = 0; k < 4; ++k) h.vinc[fill[h.tets[4 * (size_t)e + k]]++] = e * 4 + k;
   }
+  // ---- Algorithm 1 (§4.8): interface triangles.  The element across a face is the other
+  // element holding all three of its vertices, found among the elements of its first
+  // vertex; a fluid face whose twin belongs to a wall element is an interface triangle.
+  std::vector<int32_t> twin((size_t)E * 4, -1);  // element across each face
+  std::atomic<bool> bad_face{false};
+  parallel_ranges(E, [&](int64_t e0, int64_t e1) {
+    bool bad = false;
+    for (int64_t e = e0; e < e1; ++e)
+      for (int f = 0; f < 4; ++f) {
+        const int32_t a = h.tets[4 * e + kTetFace[f][0]], b = h.tets[4 * e + kTetFace[f][1]],
+                      c = h.tets[4 * e + kTetFace[f][2]];
+        int found = 0;
+        for (int p = h.vinc_ptr[a]; p < h.vinc_ptr[a + 1]; ++p) {
+          const int32_t o = h.vinc[p] >> 2;
+          if (o == e) continue;
+          const int32_t* t = &h.tets[4 * (size_t)o];
+          const bool hb = t[0] == b || t[1] == b || t[2] == b || t[3] == b;
+          const bool hc = t[0] == c || t[1] == c || t[2] == c || t[3] == c;
+          if (hb && hc) {
+            twin[4 * e + f] = o;
+            ++found;
+          }
+        }
+        if (found > 1) bad = true;
+      }
+    if (bad) bad_face.store(true);
+  });
+  if (bad_face.load()) return "a face is shared by more than two elements";
   h.iface.clear();
   for (int e = 0; e < E; ++e) {
     if (h.dom[e] != 0) continue;
@@ -92,45 +128,51 @@ std::string build_topology(HostSetup& h) {
       rk[4] = rk[5] = rk[6] = RK_DIR;
     }
   }
-  // ---- block pattern: unique sorted (row, col) pairs of vertices sharing an element
-  std::vector<int64_t> pairs;
-  pairs.reserve((size_t)E * 16 + V);
-  for (int v = 0; v < V; ++v) pairs.push_back((int64_t)v * V + v);
-  for (int e = 0; e < E; ++e)
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) pairs.push_back((int64_t)h.tets[4 * e + i] * V + h.tets[4 * e + j]);
-  std::sort(pairs.begin(), pairs.end());
-  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  // ---- block pattern: row v holds v and every vertex of an element holding v, ascending
   h.rowptr.assign(V + 1, 0);
-  h.colind.resize(pairs.size());
-  for (size_t k = 0; k < pairs.size(); ++k) {
-    h.rowptr[pairs[k] / V + 1]++;
-    h.colind[k] = (int32_t)(pairs[k] % V);
+  auto row_cols = [&](int v, std::vector<int32_t>& cols) {
+    cols.clear();
+    cols.push_back(v);
+    for (int p = h.vinc_ptr[v]; p < h.vinc_ptr[v + 1]; ++p) {
+      const int32_t* t = &h.tets[4 * (size_t)(h.vinc[p] >> 2)];
+      cols.insert(cols.end(), t, t + 4);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  };
+  parallel_ranges(V, [&](int64_t v0, int64_t v1) {
+    std::vector<int32_t> cols;
+    for (int64_t v = v0; v < v1; ++v) {
+      row_cols((int)v, cols);
+      h.rowptr[v + 1] = (int32_t)cols.size();
+    }
+  });
+  for (int v = 0; v < V; ++v) {
+    if ((int64_t)h.rowptr[v + 1] + h.rowptr[v] > INT_MAX) return "block pattern exceeds 2^31 blocks";
+    h.rowptr[v + 1] += h.rowptr[v];
   }
-  for (int v = 0; v < V; ++v) h.rowptr[v + 1] += h.rowptr[v];
-  // ---- residual gather map (ascending element order in every list)
-  h.vinc_ptr.assign(V + 1, 0);
-  for (int e = 0; e < E; ++e)
-    for (int k = 0; k < 4; ++k) h.vinc_ptr[h.tets[4 * e + k] + 1]++;
-  for (int v = 0; v < V; ++v) h.vinc_ptr[v + 1] += h.vinc_ptr[v];
-  h.vinc.resize((size_t)E * 4);
-  {
-    std::vector<int32_t> fill(h.vinc_ptr.begin(), h.vinc_ptr.end() - 1);
-    for (int e = 0; e < E; ++e)
-      for (int k = 0; k < 4; ++k) h.vinc[fill[h.tets[4 * e + k]]++] = e * 4 + k;
-  }
+  h.colind.resize(h.rowptr[V]);
+  parallel_ranges(V, [&](int64_t v0, int64_t v1) {
+    std::vector<int32_t> cols;
+    for (int64_t v = v0; v < v1; ++v) {
+      row_cols((int)v, cols);
+      std::copy(cols.begin(), cols.end(), h.colind.begin() + h.rowptr[v]);
+    }
+  });
   // ---- Jacobian scatter: the block of every (element, local row vertex, local column vertex)
   h.elem_blk.resize((size_t)E * 16);
-  for (int e = 0; e < E; ++e)
-    for (int a = 0; a < 4; ++a) {
-      int va = h.tets[4 * e + a];
-      const int32_t* c0 = &h.colind[h.rowptr[va]];
-      const int32_t* c1 = &h.colind[h.rowptr[va + 1]];
-      for (int b = 0; b < 4; ++b) {
-        const int32_t* p = std::lower_bound(c0, c1, h.tets[4 * e + b]);
-        h.elem_blk[16 * (size_t)e + 4 * a + b] = (int32_t)(p - h.colind.data());
+  parallel_ranges(E, [&](int64_t e0, int64_t e1) {
+    for (int64_t e = e0; e < e1; ++e)
+      for (int a = 0; a < 4; ++a) {
+        int va = h.tets[4 * e + a];
+        const int32_t* c0 = &h.colind[h.rowptr[va]];
+        const int32_t* c1 = &h.colind[0] + h.rowptr[va + 1];
+        for (int b = 0; b < 4; ++b) {
+          const int32_t* q = std::lower_bound(c0, c1, h.tets[4 * e + b]);
+          h.elem_blk[16 * e + 4 * a + b] = (int32_t)(q - h.colind.data());
+        }
       }
-    }
+  });
   // ---- element colours, per kind: greedy in ascending element order, the least colour no
   // element sharing a vertex holds yet.  Elements of one colour touch disjoint block rows
   // and columns, so one launch per colour adds their element matrices into J without
@@ -378,6 +420,237 @@ static void onewd(const HostSetup& h, const std::vector<int32_t>& set, int sep, 
   }
 }
 
+// One subdomain's part of the concatenated set-up arrays, with its rows, blocks, levels
+// and map entries counted from zero; the parts are appended in subdomain order.
+struct SubPart {
+  std::vector<int32_t> lglob;
+  std::vector<uint8_t> lowned;
+  int nowned = 0;
+  std::vector<int32_t> lrowptr{0}, lcol, lsrc, ldiag;
+  std::vector<int32_t> fwd_sub_lvl{0}, fwd_lvl_ptr{0}, fwd_rows;
+  std::vector<int32_t> bwd_sub_lvl{0}, bwd_lvl_ptr{0}, bwd_rows;
+  std::vector<int32_t> kent_ptr{0}, piv, umap;
+  std::vector<int64_t> umap_row{0};
+  std::vector<int32_t> fwd_qslot, bwd_qslot, lslot;
+  int nslots = 0;
+  std::string err;
+};
+
+// Subdomain s: overlap rings, ordering, ILU(l) pattern, level schedules, factorization work
+// lists and sweep slots.  mark and loc are the calling thread's [V] arrays (mark may hold
+// other subdomains' numbers; loc is -1 outside the call).
+static void build_one(const HostSetup& h, const fsi_opts& o, int s, const std::vector<int32_t>& members,
+                      std::vector<int32_t>& mark, std::vector<int32_t>& loc, SubPart& P) {
+  const int L = o.ilu_level;
+  // extended set: delta rings of vertex-graph neighbours around the owned vertices
+  std::vector<int32_t> set = members;
+  for (int v : set) mark[v] = s;
+  size_t ring_begin = 0;
+  for (int d = 0; d < o.overlap; ++d) {
+    size_t ring_end = set.size();
+    for (size_t i = ring_begin; i < ring_end; ++i) {
+      int v = set[i];
+      for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
+        int u = h.colind[k];
+        if (mark[u] != s) { mark[u] = s; set.push_back(u); }
+      }
+    }
+    ring_begin = ring_end;
+  }
+  std::vector<int32_t> order;
+  if (o.ordering == FSI_ORDER_1WD)
+    onewd(h, set, o.ilu_level + 3, order);  // separators beyond the kept fill level apart
+  else
+    rcm(h, set, order);
+  const int m = (int)order.size();
+  const int base = (int)P.lglob.size();
+  for (int l = 0; l < m; ++l) loc[order[l]] = l;
+  for (int l = 0; l < m; ++l) {
+    P.lglob.push_back(order[l]);
+    uint8_t own = h.part[order[l]] == s;
+    P.lowned.push_back(own);
+    P.nowned += own;
+  }
+  // ILU(l) pattern by levels of fill: row by row, pivots in ascending order through a
+  // min-heap; lev(i,j) = min over pivots k of lev(i,k) + lev(k,j) + 1, kept if <= l.
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rowpat(m);  // (col, level), sorted
+  std::vector<int32_t> lev(m, INT_MAX);
+  std::vector<int32_t> srcb(m, -1);
+  for (int i = 0; i < m; ++i) {
+    int g = order[i];
+    std::vector<int32_t> cols;
+    std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
+    for (int k = h.rowptr[g]; k < h.rowptr[g + 1]; ++k) {
+      int u = h.colind[k];
+      if (mark[u] != s) continue;
+      int c = loc[u];
+      lev[c] = 0;
+      srcb[c] = k;
+      cols.push_back(c);
+      if (c < i) heap.push(c);
+    }
+    int last = -1;
+    while (L > 0 && !heap.empty()) {
+      int k = heap.top();
+      heap.pop();
+      if (k == last) continue;
+      last = k;
+      for (const auto& kj : rowpat[k]) {
+        if (kj.first <= k) continue;
+        int nl = lev[k] + kj.second + 1;
+        if (nl > L) continue;
+        int j = kj.first;
+        if (lev[j] == INT_MAX) {
+          lev[j] = nl;
+          cols.push_back(j);
+          if (j < i) heap.push(j);
+        } else if (nl < lev[j]) {
+          lev[j] = nl;
+        }
+      }
+    }
+    std::sort(cols.begin(), cols.end());
+    for (int c : cols) {
+      rowpat[i].push_back({c, lev[c]});
+      if (c == i) P.ldiag.push_back((int32_t)P.lcol.size());
+      P.lcol.push_back(base + c);
+      P.lsrc.push_back(srcb[c]);
+    }
+    for (int c : cols) { lev[c] = INT_MAX; srcb[c] = -1; }
+    P.lrowptr.push_back((int32_t)P.lcol.size());
+    if ((int)P.ldiag.size() != base + i + 1) { P.err = "missing diagonal block"; return; }
+  }
+  for (int l = 0; l < m; ++l) loc[order[l]] = -1;
+  // level schedules of the two triangular sweeps
+  auto rowb = [&](int i) { return P.lrowptr[base + i]; };
+  auto rowe = [&](int i) { return P.lrowptr[base + i + 1]; };
+  std::vector<int32_t> lf(m, 0), lb(m, 0);
+  int nf = 0, nbk = 0;
+  for (int i = 0; i < m; ++i) {
+    int lv = 0;
+    for (int p = rowb(i); p < P.ldiag[base + i]; ++p) lv = std::max(lv, lf[P.lcol[p] - base] + 1);
+    lf[i] = lv;
+    nf = std::max(nf, lv + 1);
+  }
+  for (int i = m - 1; i >= 0; --i) {
+    int lv = 0;
+    for (int p = P.ldiag[base + i] + 1; p < rowe(i); ++p) lv = std::max(lv, lb[P.lcol[p] - base] + 1);
+    lb[i] = lv;
+    nbk = std::max(nbk, lv + 1);
+  }
+  auto emit = [&](const std::vector<int32_t>& lv, int nlev, std::vector<int32_t>& lvl_ptr,
+                  std::vector<int32_t>& rows, std::vector<int32_t>& sub_lvl) {
+    std::vector<int32_t> cnt(nlev + 1, 0);
+    for (int i = 0; i < m; ++i) cnt[lv[i] + 1]++;
+    for (int l = 0; l < nlev; ++l) cnt[l + 1] += cnt[l];
+    size_t r0 = rows.size();
+    rows.resize(r0 + m);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int i = 0; i < m; ++i) rows[r0 + fill[lv[i]]++] = base + i;
+    for (int l = 0; l < nlev; ++l) lvl_ptr.push_back((int32_t)(r0 + cnt[l + 1]));
+    sub_lvl.push_back((int32_t)lvl_ptr.size() - 1);
+  };
+  emit(lf, nf, P.fwd_lvl_ptr, P.fwd_rows, P.fwd_sub_lvl);
+  emit(lb, nbk, P.bwd_lvl_ptr, P.bwd_rows, P.bwd_sub_lvl);
+  // factorization work lists: for each row i, its L blocks (ascending k) as pivots
+  // {position of A_ik in row i, D_k, length of U_k, offset of U_k's map}; the map gives,
+  // for every block U_kj of row k, 1 + the position of A_ij in row i, or 0 when (i, j)
+  // is not in the pattern
+  for (int i = 0; i < m; ++i) {
+    const int32_t* ci0 = &P.lcol[rowb(i)];
+    const int32_t* ci1 = &P.lcol[0] + rowe(i);
+    for (int p = rowb(i); p < P.ldiag[base + i]; ++p) {
+      const int k = P.lcol[p] - base;
+      const int u0 = P.ldiag[base + k] + 1, u1 = rowe(k);
+      P.piv.insert(P.piv.end(), {p - rowb(i), P.ldiag[base + k], u1 - u0,
+                                 (int32_t)((int64_t)P.umap.size() - P.umap_row.back())});
+      const int32_t* f = ci0;
+      for (int q = u0; q < u1; ++q) {  // both column lists ascend: one merge walk
+        f = std::lower_bound(f, ci1, P.lcol[q]);
+        P.umap.push_back(f != ci1 && *f == P.lcol[q] ? (int32_t)(f - ci0) + 1 : 0);
+      }
+    }
+    P.kent_ptr.push_back((int32_t)(P.piv.size() / 4));
+    P.umap_row.push_back((int64_t)P.umap.size());
+  }
+  // LDS slots for the sweeps: y_k (forward) or x_k (backward) is live from its own level
+  // to the level of its last reader; slots are handed out greedily in level order and
+  // returned once their last reader's level has passed (barrier in between).
+  auto colour = [&](const std::vector<int32_t>& lv, bool bwd, std::vector<int32_t>& qslot,
+                    const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows_sched,
+                    int lvl_base, int nlev) {
+    std::vector<int32_t> last(m, -1);
+    for (int i = 0; i < m; ++i) {
+      const int pb = bwd ? P.ldiag[base + i] + 1 : rowb(i);
+      const int pe = bwd ? rowe(i) : P.ldiag[base + i];
+      for (int p = pb; p < pe; ++p) {
+        const int k = P.lcol[p] - base;
+        last[k] = std::max(last[k], lv[i]);
+      }
+    }
+    std::vector<int32_t> slot(m, -1);
+    std::vector<std::vector<int32_t>> release(nlev + 1);
+    std::vector<int32_t> freel;
+    int used = 0;
+    for (int L = 0; L < nlev; ++L) {
+      for (int sidx : release[L]) freel.push_back(sidx);
+      for (int q = lvl_ptr[lvl_base + L]; q < lvl_ptr[lvl_base + L + 1]; ++q) {
+        const int i = rows_sched[q] - base;
+        if (last[i] < 0) continue;  // nobody in this sweep reads the row
+        int sidx;
+        if (!freel.empty()) { sidx = freel.back(); freel.pop_back(); }
+        else sidx = used++;
+        slot[i] = sidx;
+        release[last[i] + 1].push_back(sidx);
+      }
+    }
+    for (int q = lvl_ptr[lvl_base]; q < lvl_ptr[lvl_base + nlev]; ++q) qslot[q] = slot[rows_sched[q] - base];
+    for (int i = 0; i < m; ++i) {
+      const int pb = bwd ? P.ldiag[base + i] + 1 : rowb(i);
+      const int pe = bwd ? rowe(i) : P.ldiag[base + i];
+      for (int p = pb; p < pe; ++p) P.lslot[p] = slot[P.lcol[p] - base];
+    }
+    P.nslots = std::max(P.nslots, used);
+  };
+  P.lslot.resize(P.lcol.size(), -1);
+  P.fwd_qslot.resize(P.fwd_rows.size(), -1);
+  P.bwd_qslot.resize(P.bwd_rows.size(), -1);
+  colour(lf, false, P.fwd_qslot, P.fwd_lvl_ptr, P.fwd_rows, 0, nf);
+  colour(lb, true, P.bwd_qslot, P.bwd_lvl_ptr, P.bwd_rows, 0, nbk);
+}
+
+static void append_part(HostSetup& h, int s, const SubPart& P) {
+  const int32_t rb = (int32_t)h.lglob.size(), bb = (int32_t)h.lcol.size();
+  h.lglob.insert(h.lglob.end(), P.lglob.begin(), P.lglob.end());
+  h.lowned.insert(h.lowned.end(), P.lowned.begin(), P.lowned.end());
+  h.sub_nowned[s] = P.nowned;
+  for (size_t i = 1; i < P.lrowptr.size(); ++i) h.lrowptr.push_back(P.lrowptr[i] + bb);
+  for (int32_t c : P.lcol) h.lcol.push_back(c + rb);
+  h.lsrc.insert(h.lsrc.end(), P.lsrc.begin(), P.lsrc.end());
+  for (int32_t d : P.ldiag) h.ldiag.push_back(d + bb);
+  auto levels = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows, std::vector<int32_t>& hlp,
+                    std::vector<int32_t>& hrows, std::vector<int32_t>& hsub) {
+    const int32_t r0 = (int32_t)hrows.size();
+    for (int32_t r : rows) hrows.push_back(r + rb);
+    for (size_t l = 1; l < lp.size(); ++l) hlp.push_back(lp[l] + r0);
+    hsub.push_back((int32_t)hlp.size() - 1);
+  };
+  levels(P.fwd_lvl_ptr, P.fwd_rows, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl);
+  levels(P.bwd_lvl_ptr, P.bwd_rows, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl);
+  const int32_t kb = (int32_t)(h.piv.size() / 4);
+  for (size_t q = 0; q < P.piv.size(); q += 4)
+    h.piv.insert(h.piv.end(), {P.piv[q], P.piv[q + 1] + bb, P.piv[q + 2], P.piv[q + 3]});
+  for (size_t i = 1; i < P.kent_ptr.size(); ++i) h.kent_ptr.push_back(P.kent_ptr[i] + kb);
+  const int64_t ub = (int64_t)h.umap.size();
+  h.umap.insert(h.umap.end(), P.umap.begin(), P.umap.end());
+  for (size_t i = 1; i < P.umap_row.size(); ++i) h.umap_row.push_back(P.umap_row[i] + ub);
+  h.lslot.insert(h.lslot.end(), P.lslot.begin(), P.lslot.end());
+  h.fwd_qslot.insert(h.fwd_qslot.end(), P.fwd_qslot.begin(), P.fwd_qslot.end());
+  h.bwd_qslot.insert(h.bwd_qslot.end(), P.bwd_qslot.begin(), P.bwd_qslot.end());
+  h.nslots = std::max(h.nslots, P.nslots);
+  h.sub_row_off[s + 1] = (int32_t)h.lglob.size();
+}
+
 std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
   const int V = h.V, ns = o.nsub;
   h.ns = ns;
@@ -410,191 +683,58 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
   h.umap.clear();
   h.umap_row.assign(1, 0);
 
-  std::vector<int32_t> owners_of(V);
   std::vector<std::vector<int32_t>> members(ns);
   for (int v = 0; v < V; ++v) members[h.part[v]].push_back(v);
-  std::vector<int32_t> mark(V, -1), loc(V, -1);
-  const int L = o.ilu_level;
-  for (int s = 0; s < ns; ++s) {
-    // extended set: delta rings of vertex-graph neighbours around the owned vertices
-    std::vector<int32_t> set = members[s];
-    for (int v : set) mark[v] = s;
-    size_t ring_begin = 0;
-    for (int d = 0; d < o.overlap; ++d) {
-      size_t ring_end = set.size();
-      for (size_t i = ring_begin; i < ring_end; ++i) {
-        int v = set[i];
-        for (int k = h.rowptr[v]; k < h.rowptr[v + 1]; ++k) {
-          int u = h.colind[k];
-          if (mark[u] != s) { mark[u] = s; set.push_back(u); }
-        }
+  // Subdomains are built by worker threads, at most `window` ahead of the one being
+  // appended, and appended in order by this thread; each is built exactly as it would be
+  // alone, so the products do not depend on the thread count.
+  const int T = std::max(1, std::min(setup_threads(), ns));
+  const int window = 4 * T;
+  std::vector<std::unique_ptr<SubPart>> done(ns);
+  std::mutex mu;
+  std::condition_variable cv;
+  int next_take = 0, next_append = 0;
+  bool stop = false;
+  auto worker = [&] {
+    std::vector<int32_t> mark(V, -1), loc(V, -1);
+    for (;;) {
+      int s;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || next_take >= ns || next_take < next_append + window; });
+        if (stop || next_take >= ns) return;
+        s = next_take++;
       }
-      ring_begin = ring_end;
+      auto P = std::make_unique<SubPart>();
+      build_one(h, o, s, members[s], mark, loc, *P);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        done[s] = std::move(P);
+      }
+      cv.notify_all();
     }
-    std::vector<int32_t> order;
-    if (o.ordering == FSI_ORDER_1WD)
-      onewd(h, set, o.ilu_level + 3, order);  // separators beyond the kept fill level apart
-    else
-      rcm(h, set, order);
-    const int m = (int)order.size();
-    const int base = (int)h.lglob.size();
-    for (int l = 0; l < m; ++l) loc[order[l]] = l;
-    for (int l = 0; l < m; ++l) {
-      h.lglob.push_back(order[l]);
-      uint8_t own = h.part[order[l]] == s;
-      h.lowned.push_back(own);
-      h.sub_nowned[s] += own;
+  };
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back(worker);
+  std::string err;
+  for (int s = 0; s < ns && err.empty(); ++s) {
+    std::unique_ptr<SubPart> P;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return done[s] != nullptr; });
+      P = std::move(done[s]);
     }
-    // ILU(l) pattern by levels of fill: row by row, pivots in ascending order through a
-    // min-heap; lev(i,j) = min over pivots k of lev(i,k) + lev(k,j) + 1, kept if <= l.
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> rowpat(m);  // (col, level), sorted
-    std::vector<int32_t> lev(m, INT_MAX);
-    std::vector<int32_t> srcb(m, -1);
-    for (int i = 0; i < m; ++i) {
-      int g = order[i];
-      std::vector<int32_t> cols;
-      std::priority_queue<int32_t, std::vector<int32_t>, std::greater<int32_t>> heap;
-      for (int k = h.rowptr[g]; k < h.rowptr[g + 1]; ++k) {
-        int u = h.colind[k];
-        if (mark[u] != s) continue;
-        int c = loc[u];
-        lev[c] = 0;
-        srcb[c] = k;
-        cols.push_back(c);
-        if (c < i) heap.push(c);
-      }
-      int last = -1;
-      while (L > 0 && !heap.empty()) {
-        int k = heap.top();
-        heap.pop();
-        if (k == last) continue;
-        last = k;
-        for (const auto& kj : rowpat[k]) {
-          if (kj.first <= k) continue;
-          int nl = lev[k] + kj.second + 1;
-          if (nl > L) continue;
-          int j = kj.first;
-          if (lev[j] == INT_MAX) {
-            lev[j] = nl;
-            cols.push_back(j);
-            if (j < i) heap.push(j);
-          } else if (nl < lev[j]) {
-            lev[j] = nl;
-          }
-        }
-      }
-      std::sort(cols.begin(), cols.end());
-      for (int c : cols) {
-        rowpat[i].push_back({c, lev[c]});
-        if (c == i) h.ldiag.push_back((int32_t)h.lcol.size());
-        h.lcol.push_back(base + c);
-        h.lsrc.push_back(srcb[c]);
-      }
-      for (int c : cols) { lev[c] = INT_MAX; srcb[c] = -1; }
-      h.lrowptr.push_back((int32_t)h.lcol.size());
-      if ((int)h.ldiag.size() != base + i + 1) return "missing diagonal block";
+    if (!P->err.empty()) err = P->err;
+    else append_part(h, s, *P);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      next_append = s + 1;
+      if (!err.empty()) stop = true;
     }
-    for (int l = 0; l < m; ++l) loc[order[l]] = -1;
-    // level schedules of the two triangular sweeps
-    auto rowb = [&](int i) { return h.lrowptr[base + i]; };
-    auto rowe = [&](int i) { return h.lrowptr[base + i + 1]; };
-    std::vector<int32_t> lf(m, 0), lb(m, 0);
-    int nf = 0, nbk = 0;
-    for (int i = 0; i < m; ++i) {
-      int lv = 0;
-      for (int p = rowb(i); p < h.ldiag[base + i]; ++p) lv = std::max(lv, lf[h.lcol[p] - base] + 1);
-      lf[i] = lv;
-      nf = std::max(nf, lv + 1);
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      int lv = 0;
-      for (int p = h.ldiag[base + i] + 1; p < rowe(i); ++p) lv = std::max(lv, lb[h.lcol[p] - base] + 1);
-      lb[i] = lv;
-      nbk = std::max(nbk, lv + 1);
-    }
-    auto emit = [&](const std::vector<int32_t>& lv, int nlev, std::vector<int32_t>& lvl_ptr,
-                    std::vector<int32_t>& rows, std::vector<int32_t>& sub_lvl) {
-      std::vector<int32_t> cnt(nlev + 1, 0);
-      for (int i = 0; i < m; ++i) cnt[lv[i] + 1]++;
-      for (int l = 0; l < nlev; ++l) cnt[l + 1] += cnt[l];
-      size_t r0 = rows.size();
-      rows.resize(r0 + m);
-      std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-      for (int i = 0; i < m; ++i) rows[r0 + fill[lv[i]]++] = base + i;
-      for (int l = 0; l < nlev; ++l) lvl_ptr.push_back((int32_t)(r0 + cnt[l + 1]));
-      sub_lvl.push_back((int32_t)lvl_ptr.size() - 1);
-    };
-    emit(lf, nf, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl);
-    emit(lb, nbk, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl);
-    // factorization work lists: for each row i, its L blocks (ascending k) as pivots
-    // {position of A_ik in row i, D_k, length of U_k, offset of U_k's map}; the map gives,
-    // for every block U_kj of row k, 1 + the position of A_ij in row i, or 0 when (i, j)
-    // is not in the pattern
-    for (int i = 0; i < m; ++i) {
-      const int32_t* ci0 = &h.lcol[rowb(i)];
-      const int32_t* ci1 = &h.lcol[0] + rowe(i);
-      for (int p = rowb(i); p < h.ldiag[base + i]; ++p) {
-        const int k = h.lcol[p] - base;
-        const int u0 = h.ldiag[base + k] + 1, u1 = rowe(k);
-        h.piv.insert(h.piv.end(), {p - rowb(i), h.ldiag[base + k], u1 - u0,
-                                   (int32_t)((int64_t)h.umap.size() - h.umap_row.back())});
-        const int32_t* f = ci0;
-        for (int q = u0; q < u1; ++q) {  // both column lists ascend: one merge walk
-          f = std::lower_bound(f, ci1, h.lcol[q]);
-          h.umap.push_back(f != ci1 && *f == h.lcol[q] ? (int32_t)(f - ci0) + 1 : 0);
-        }
-      }
-      h.kent_ptr.push_back((int32_t)(h.piv.size() / 4));
-      h.umap_row.push_back((int64_t)h.umap.size());
-    }
-    // LDS slots for the sweeps: y_k (forward) or x_k (backward) is live from its own level
-    // to the level of its last reader; slots are handed out greedily in level order and
-    // returned once their last reader's level has passed (barrier in between).
-    auto colour = [&](const std::vector<int32_t>& lv, bool bwd, std::vector<int32_t>& qslot,
-                      const std::vector<int32_t>& lvl_ptr, const std::vector<int32_t>& rows_sched,
-                      int lvl_base, int nlev) {
-      std::vector<int32_t> last(m, -1);
-      for (int i = 0; i < m; ++i) {
-        const int pb = bwd ? h.ldiag[base + i] + 1 : rowb(i);
-        const int pe = bwd ? rowe(i) : h.ldiag[base + i];
-        for (int p = pb; p < pe; ++p) {
-          const int k = h.lcol[p] - base;
-          last[k] = std::max(last[k], lv[i]);
-        }
-      }
-      std::vector<int32_t> slot(m, -1);
-      std::vector<std::vector<int32_t>> release(nlev + 1);
-      std::vector<int32_t> freel;
-      int used = 0;
-      for (int L = 0; L < nlev; ++L) {
-        for (int sidx : release[L]) freel.push_back(sidx);
-        for (int q = lvl_ptr[lvl_base + L]; q < lvl_ptr[lvl_base + L + 1]; ++q) {
-          const int i = rows_sched[q] - base;
-          if (last[i] < 0) continue;  // nobody in this sweep reads the row
-          int sidx;
-          if (!freel.empty()) { sidx = freel.back(); freel.pop_back(); }
-          else sidx = used++;
-          slot[i] = sidx;
-          release[last[i] + 1].push_back(sidx);
-        }
-      }
-      for (int q = lvl_ptr[lvl_base]; q < lvl_ptr[lvl_base + nlev]; ++q) qslot[q] = slot[rows_sched[q] - base];
-      for (int i = 0; i < m; ++i) {
-        const int pb = bwd ? h.ldiag[base + i] + 1 : rowb(i);
-        const int pe = bwd ? rowe(i) : h.ldiag[base + i];
-        for (int p = pb; p < pe; ++p) h.lslot[p] = slot[h.lcol[p] - base];
-      }
-      h.nslots = std::max(h.nslots, used);
-    };
-    h.lslot.resize(h.lcol.size(), -1);
-    h.fwd_qslot.resize(h.fwd_rows.size(), -1);
-    h.bwd_qslot.resize(h.bwd_rows.size(), -1);
-    colour(lf, false, h.fwd_qslot, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl[s], nf);
-    colour(lb, true, h.bwd_qslot, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl[s], nbk);
-    h.sub_row_off[s + 1] = (int32_t)h.lglob.size();
+    cv.notify_all();
   }
-  (void)owners_of;
-  return "";
+  for (auto& t : th) t.join();
+  return err;
 }
 
 }  // namespace fsi
