@@ -619,36 +619,43 @@ static void build_one(const HostSetup& h, const fsi_opts& o, int s, const std::v
   colour(lb, true, P.bwd_qslot, P.bwd_lvl_ptr, P.bwd_rows, 0, nbk);
 }
 
-static void append_part(HostSetup& h, int s, const SubPart& P) {
-  const int32_t rb = (int32_t)h.lglob.size(), bb = (int32_t)h.lcol.size();
-  h.lglob.insert(h.lglob.end(), P.lglob.begin(), P.lglob.end());
-  h.lowned.insert(h.lowned.end(), P.lowned.begin(), P.lowned.end());
+// Where part s goes in the concatenated arrays: its first row, block, schedule row, level
+// pointer, pivot entry and map entry.
+struct PartOffsets {
+  int64_t row = 0, blk = 0, frow = 0, flvl = 0, brow = 0, blvl = 0, piv = 0, umap = 0;
+};
+
+static void copy_part(HostSetup& h, int s, const SubPart& P, const PartOffsets& O) {
+  const int32_t rb = (int32_t)O.row, bb = (int32_t)O.blk;
+  std::copy(P.lglob.begin(), P.lglob.end(), h.lglob.begin() + O.row);
+  std::copy(P.lowned.begin(), P.lowned.end(), h.lowned.begin() + O.row);
   h.sub_nowned[s] = P.nowned;
-  for (size_t i = 1; i < P.lrowptr.size(); ++i) h.lrowptr.push_back(P.lrowptr[i] + bb);
-  for (int32_t c : P.lcol) h.lcol.push_back(c + rb);
-  h.lsrc.insert(h.lsrc.end(), P.lsrc.begin(), P.lsrc.end());
-  for (int32_t d : P.ldiag) h.ldiag.push_back(d + bb);
-  auto levels = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows, std::vector<int32_t>& hlp,
-                    std::vector<int32_t>& hrows, std::vector<int32_t>& hsub) {
-    const int32_t r0 = (int32_t)hrows.size();
-    for (int32_t r : rows) hrows.push_back(r + rb);
-    for (size_t l = 1; l < lp.size(); ++l) hlp.push_back(lp[l] + r0);
-    hsub.push_back((int32_t)hlp.size() - 1);
+  for (size_t i = 1; i < P.lrowptr.size(); ++i) h.lrowptr[O.row + i] = P.lrowptr[i] + bb;
+  for (size_t k = 0; k < P.lcol.size(); ++k) h.lcol[O.blk + k] = P.lcol[k] + rb;
+  std::copy(P.lsrc.begin(), P.lsrc.end(), h.lsrc.begin() + O.blk);
+  std::copy(P.lslot.begin(), P.lslot.end(), h.lslot.begin() + O.blk);
+  for (size_t i = 0; i < P.ldiag.size(); ++i) h.ldiag[O.row + i] = P.ldiag[i] + bb;
+  auto levels = [&](const std::vector<int32_t>& lp, const std::vector<int32_t>& rows, const std::vector<int32_t>& qs,
+                    std::vector<int32_t>& hlp, std::vector<int32_t>& hrows, std::vector<int32_t>& hqs,
+                    std::vector<int32_t>& hsub, int64_t r0, int64_t l0) {
+    for (size_t q = 0; q < rows.size(); ++q) hrows[r0 + q] = rows[q] + rb;
+    std::copy(qs.begin(), qs.end(), hqs.begin() + r0);
+    for (size_t l = 1; l < lp.size(); ++l) hlp[l0 + l] = lp[l] + (int32_t)r0;
+    hsub[s + 1] = (int32_t)(l0 + lp.size() - 1);
   };
-  levels(P.fwd_lvl_ptr, P.fwd_rows, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_sub_lvl);
-  levels(P.bwd_lvl_ptr, P.bwd_rows, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_sub_lvl);
-  const int32_t kb = (int32_t)(h.piv.size() / 4);
-  for (size_t q = 0; q < P.piv.size(); q += 4)
-    h.piv.insert(h.piv.end(), {P.piv[q], P.piv[q + 1] + bb, P.piv[q + 2], P.piv[q + 3]});
-  for (size_t i = 1; i < P.kent_ptr.size(); ++i) h.kent_ptr.push_back(P.kent_ptr[i] + kb);
-  const int64_t ub = (int64_t)h.umap.size();
-  h.umap.insert(h.umap.end(), P.umap.begin(), P.umap.end());
-  for (size_t i = 1; i < P.umap_row.size(); ++i) h.umap_row.push_back(P.umap_row[i] + ub);
-  h.lslot.insert(h.lslot.end(), P.lslot.begin(), P.lslot.end());
-  h.fwd_qslot.insert(h.fwd_qslot.end(), P.fwd_qslot.begin(), P.fwd_qslot.end());
-  h.bwd_qslot.insert(h.bwd_qslot.end(), P.bwd_qslot.begin(), P.bwd_qslot.end());
-  h.nslots = std::max(h.nslots, P.nslots);
-  h.sub_row_off[s + 1] = (int32_t)h.lglob.size();
+  levels(P.fwd_lvl_ptr, P.fwd_rows, P.fwd_qslot, h.fwd_lvl_ptr, h.fwd_rows, h.fwd_qslot, h.fwd_sub_lvl, O.frow, O.flvl);
+  levels(P.bwd_lvl_ptr, P.bwd_rows, P.bwd_qslot, h.bwd_lvl_ptr, h.bwd_rows, h.bwd_qslot, h.bwd_sub_lvl, O.brow, O.blvl);
+  for (size_t q = 0; q < P.piv.size(); q += 4) {
+    int32_t* d = &h.piv[4 * O.piv + q];
+    d[0] = P.piv[q];
+    d[1] = P.piv[q + 1] + bb;
+    d[2] = P.piv[q + 2];
+    d[3] = P.piv[q + 3];
+  }
+  for (size_t i = 1; i < P.kent_ptr.size(); ++i) h.kent_ptr[O.row + i] = P.kent_ptr[i] + (int32_t)O.piv;
+  std::copy(P.umap.begin(), P.umap.end(), h.umap.begin() + O.umap);
+  for (size_t i = 1; i < P.umap_row.size(); ++i) h.umap_row[O.row + i] = P.umap_row[i] + O.umap;
+  h.sub_row_off[s + 1] = (int32_t)(O.row + P.lglob.size());
 }
 
 std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
@@ -685,56 +692,83 @@ std::string build_subdomains(HostSetup& h, const fsi_opts& o) {
 
   std::vector<std::vector<int32_t>> members(ns);
   for (int v = 0; v < V; ++v) members[h.part[v]].push_back(v);
-  // Subdomains are built by worker threads, at most `window` ahead of the one being
-  // appended, and appended in order by this thread; each is built exactly as it would be
-  // alone, so the products do not depend on the thread count.
-  const int T = std::max(1, std::min(setup_threads(), ns));
-  const int window = 4 * T;
-  std::vector<std::unique_ptr<SubPart>> done(ns);
-  std::mutex mu;
-  std::condition_variable cv;
-  int next_take = 0, next_append = 0;
-  bool stop = false;
-  auto worker = [&] {
-    std::vector<int32_t> mark(V, -1), loc(V, -1);
-    for (;;) {
-      int s;
-      {
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] { return stop || next_take >= ns || next_take < next_append + window; });
-        if (stop || next_take >= ns) return;
-        s = next_take++;
-      }
-      auto P = std::make_unique<SubPart>();
-      build_one(h, o, s, members[s], mark, loc, *P);
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        done[s] = std::move(P);
-      }
-      cv.notify_all();
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 0; t < T; ++t) th.emplace_back(worker);
-  std::string err;
-  for (int s = 0; s < ns && err.empty(); ++s) {
-    std::unique_ptr<SubPart> P;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return done[s] != nullptr; });
-      P = std::move(done[s]);
-    }
-    if (!P->err.empty()) err = P->err;
-    else append_part(h, s, *P);
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      next_append = s + 1;
-      if (!err.empty()) stop = true;
-    }
-    cv.notify_all();
+  // Each subdomain is built alone by a worker thread into its own part; the parts are then
+  // copied into the concatenated arrays at offsets fixed by the subdomain order, so the
+  // products do not depend on the thread count.
+  std::vector<std::unique_ptr<SubPart>> parts(ns);
+  {
+    // largest subdomains first, so that the last ones to finish are small
+    std::vector<int32_t> by_size(ns);
+    std::iota(by_size.begin(), by_size.end(), 0);
+    std::stable_sort(by_size.begin(), by_size.end(),
+                     [&](int a, int b) { return members[a].size() > members[b].size(); });
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    const int T = std::max(1, std::min(setup_threads(), ns));
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&] {
+        std::vector<int32_t> mark(V, -1), loc(V, -1);
+        for (int q; (q = next.fetch_add(1)) < ns;) {
+          const int s = by_size[q];
+          parts[s] = std::make_unique<SubPart>();
+          build_one(h, o, s, members[s], mark, loc, *parts[s]);
+        }
+      });
+    for (auto& t : th) t.join();
   }
-  for (auto& t : th) t.join();
-  return err;
+  for (int s = 0; s < ns; ++s)
+    if (!parts[s]->err.empty()) return parts[s]->err;
+  std::vector<PartOffsets> off(ns + 1);
+  for (int s = 0; s < ns; ++s) {
+    const SubPart& P = *parts[s];
+    PartOffsets& a = off[s + 1];
+    a = off[s];
+    a.row += P.lglob.size();
+    a.blk += P.lcol.size();
+    a.frow += P.fwd_rows.size();
+    a.flvl += P.fwd_lvl_ptr.size() - 1;
+    a.brow += P.bwd_rows.size();
+    a.blvl += P.bwd_lvl_ptr.size() - 1;
+    a.piv += P.piv.size() / 4;
+    a.umap += P.umap.size();
+    h.nslots = std::max(h.nslots, P.nslots);
+  }
+  const PartOffsets& tot = off[ns];
+  if (tot.row > INT_MAX || tot.blk > INT_MAX || tot.piv > INT_MAX / 4)
+    return "the subdomains' local rows, blocks or pivots exceed 2^31";
+  h.lglob.resize(tot.row);
+  h.lowned.resize(tot.row);
+  h.lrowptr.assign(tot.row + 1, 0);
+  h.ldiag.resize(tot.row);
+  h.kent_ptr.assign(tot.row + 1, 0);
+  h.umap_row.assign(tot.row + 1, 0);
+  h.lcol.resize(tot.blk);
+  h.lsrc.resize(tot.blk);
+  h.lslot.resize(tot.blk);
+  h.fwd_rows.resize(tot.frow);
+  h.fwd_qslot.resize(tot.frow);
+  h.fwd_lvl_ptr.assign(tot.flvl + 1, 0);
+  h.fwd_sub_lvl.assign(ns + 1, 0);
+  h.bwd_rows.resize(tot.brow);
+  h.bwd_qslot.resize(tot.brow);
+  h.bwd_lvl_ptr.assign(tot.blvl + 1, 0);
+  h.bwd_sub_lvl.assign(ns + 1, 0);
+  h.piv.resize(4 * tot.piv);
+  h.umap.resize(tot.umap);
+  {
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    const int T = std::max(1, std::min(setup_threads(), ns));
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&] {
+        for (int s; (s = next.fetch_add(1)) < ns;) {
+          copy_part(h, s, *parts[s], off[s]);
+          parts[s].reset();
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  return "";
 }
 
 }  // namespace fsi
