@@ -94,9 +94,10 @@ typedef struct {
 } fsi_opts;
 
 /* Precision of the preconditioner application (the mixed-precision variant of §3's
- * Schwarz preconditioner).  The factorization is FP64 in every mode; FP32 and BF16 store
- * a rounded copy of the factors (round to nearest, ties to even) and run both triangular
- * sweeps in FP32 arithmetic, including accumulation.  The input v and output z of
+ * Schwarz preconditioner).  The factorization is FP64 in every mode; FP32 and BF16 round
+ * the factors (to nearest, ties to even) into the front of the FP64 factors' own buffer, so
+ * they take no memory of their own, and run both triangular sweeps in FP32 arithmetic,
+ * including accumulation.  The input v and output z of
  * fsi_pc_apply stay FP64, as do residuals, GMRES and the Newton update. */
 enum { FSI_PREC_FP64 = 0, FSI_PREC_FP32 = 1, FSI_PREC_BF16 = 2 };
 
@@ -255,7 +256,8 @@ fsi_status fsi_pc_sizes(const fsi_solver *s, int32_t *nsub, int64_t *nloc_rows,
 /* Partition, RCM-ordered subdomain vertex lists, local block patterns, and (after
  * fsi_pc_setup) the factors: strict L blocks (unit diagonal implied), strict U blocks,
  * inverted diagonal blocks in the diagonal positions, and the U diagonal blocks before
- * inversion (udiag). */
+ * inversion (udiag).  With FP32 or BF16 sweeps the factors returned are the rounded ones the
+ * sweeps use, widened to FP64 (the FP64 factors are overwritten by their rounding). */
 fsi_status fsi_pc_get(const fsi_solver *s, int32_t *part, int32_t *sub_ptr, int32_t *sub_verts,
                       int32_t *sub_nowned, int64_t *blk_ptr, int32_t *lrowptr, int32_t *lcolind,
                       double *factors, double *udiag);

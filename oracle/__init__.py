@@ -20,7 +20,8 @@ ERRORS = {0: "OK", 1: "ARG", 2: "MESH", 3: "OOM", 4: "HIP", 5: "INVERTED", 6: "Z
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with g++ -O2 -ffp-contract=off (plain IEEE FP64, no fused ops)."""
+    """Compile the oracle with g++ -O2 -ffp-contract=off (plain IEEE FP64; the only fused
+    operations are the explicit std::fma of the ILU block products)."""
     srcs = [os.path.join(_HERE, s) for s in _SRC]
     if not force and os.path.exists(_LIB):
         mt = os.path.getmtime(_LIB)

@@ -359,11 +359,15 @@ int invert7(const double* A, double* Ainv) {
   return FSIO_OK;
 }
 
-static void mm7(const double* A, const double* B, double* C) {  // C = A B
+// C = A B.  Each entry's sum runs over m in ascending order from 0, every term added to the
+// running sum with a single rounding (a fused multiply-add).  The paper states the
+// factorization in exact arithmetic; this fixes one rounding order, which any other
+// implementation can reproduce exactly.
+static void mm7(const double* A, const double* B, double* C) {
   for (int r = 0; r < 7; ++r)
     for (int c = 0; c < 7; ++c) {
       double s = 0.0;
-      for (int m = 0; m < 7; ++m) s += A[7 * r + m] * B[7 * m + c];
+      for (int m = 0; m < 7; ++m) s = std::fma(A[7 * r + m], B[7 * m + c], s);
       C[7 * r + c] = s;
     }
 }

@@ -618,8 +618,9 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
   s->umap_row = upload(s, h.umap_row);
   s->sub_row_off = upload(s, h.sub_row_off);
   s->fac = dalloc<double>(s, (size_t)s->NB * 49);
-  if (s->opts.precision == FSI_PREC_FP32) s->facs = dalloc<float>(s, (size_t)s->NB * 49);
-  if (s->opts.precision == FSI_PREC_BF16) s->facs = dalloc<uint16_t>(s, (size_t)s->NB * 49);
+  // rounded factors (FP32 or BF16 sweeps) are written over the FP64 ones after each
+  // factorization: they share its buffer
+  if (s->opts.precision != FSI_PREC_FP64) s->facs = s->fac;
   s->udiag = dalloc<double>(s, (size_t)s->R * 49);
   s->ylocal = dalloc<double>(s, (size_t)s->R * 7);
   const int mrs = s->opts.gmres_restart;
@@ -1093,7 +1094,28 @@ fsi_status fsi_pc_get(const fsi_solver* cs, int32_t* part, int32_t* sub_ptr, int
     return guard(s, [](fsi_solver* s, void* p) {
       double** a = (double**)p;
       sync(s);
-      if (a[0]) hip_ok(s, hipMemcpy(a[0], s->fac, (size_t)s->NB * 49 * sizeof(double), hipMemcpyDeviceToHost), "fac");
+      const size_t nf = (size_t)s->NB * 49;
+      if (a[0] && s->opts.precision == FSI_PREC_FP64) {
+        hip_ok(s, hipMemcpy(a[0], s->fac, nf * sizeof(double), hipMemcpyDeviceToHost), "fac");
+      } else if (a[0]) {
+        // the rounded factors the sweeps use, widened to FP64 from the last entry down (the
+        // rounded entries fill the front of the same host buffer)
+        const size_t w = s->opts.precision == FSI_PREC_FP32 ? 4 : 2;
+        hip_ok(s, hipMemcpy(a[0], s->fac, nf * w, hipMemcpyDeviceToHost), "fac");
+        unsigned char* b = (unsigned char*)a[0];
+        for (size_t i = nf; i-- > 0;) {
+          float f;
+          if (w == 4) {
+            std::memcpy(&f, b + 4 * i, 4);
+          } else {
+            uint16_t hbits;
+            std::memcpy(&hbits, b + 2 * i, 2);
+            const uint32_t u = (uint32_t)hbits << 16;
+            std::memcpy(&f, &u, 4);
+          }
+          a[0][i] = (double)f;
+        }
+      }
       if (a[1]) hip_ok(s, hipMemcpy(a[1], s->udiag, (size_t)s->R * 49 * sizeof(double), hipMemcpyDeviceToHost), "ud");
       return FSI_OK;
     }, (void*)a);

@@ -167,7 +167,7 @@ struct fsi_solver {
   int32_t *fw_ptr = nullptr, *fw_row = nullptr, *fw_lvl = nullptr;
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
-  void* facs = nullptr;  // FP32 or BF16 copy of fac for the sweeps (precision 1 or 2)
+  void* facs = nullptr;  // FP32 or BF16 factors for the sweeps (precision 1 or 2), in fac's buffer
   // Krylov / Newton work vectors
   double *Vb = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr;
   double *partial = nullptr, *hdev = nullptr, *yvdev = nullptr;

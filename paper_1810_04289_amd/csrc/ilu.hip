@@ -157,10 +157,11 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int slice, int wait_limit) {
-  // Every entry is formed as in the method's statement: sums of products in ascending
-  // order, each product rounded, nothing fused.  The block elimination of the wall rows
-  // amplifies a difference of one rounding in its input to about 1e-4 in its factors, so
-  // only the same rounded operations give factors that are reproducible anywhere else.
+  // Every entry of a block product is a sum over m in ascending order from 0, each term
+  // added with one rounding (fused multiply-add), and nothing else is fused or reordered.
+  // The block elimination of the wall rows amplifies a difference of one rounding in its
+  // input to about 1e-4 in its factors, so only the same rounded operations give factors
+  // that are reproducible anywhere else.
 #pragma clang fp contract(off)
   extern __shared__ double lds[];
   constexpr int NW = NT / 64;
@@ -253,10 +254,11 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
         double l = 0.0;
         if (pik < slice) {
 #pragma unroll
-          for (int m = 0; m < 7; ++m) l += row[pik * 49 + 7 * rr + m] * dsc[7 * m + cc];
+          for (int m = 0; m < 7; ++m) l = __builtin_fma(row[pik * 49 + 7 * rr + m], dsc[7 * m + cc], l);
         } else {
 #pragma unroll
-          for (int m = 0; m < 7; ++m) l += span_load_f64(rrow, 8 * (pik * 49 + 7 * rr + m)) * dsc[7 * m + cc];
+          for (int m = 0; m < 7; ++m)
+            l = __builtin_fma(span_load_f64(rrow, 8 * (pik * 49 + 7 * rr + m)), dsc[7 * m + cc], l);
         }
         wave_lds_sync();
         if (owner) {
@@ -270,24 +272,40 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
 #pragma unroll
           for (int m = 0; m < 7; ++m) lrow[r][m] = dsc[7 * r + m];
       }
+      // A_ij -= L_ik U_kj, column qc of the two blocks: every row's sum in ascending m; the
+      // loops run over m outside so that the fourteen sums interleave instead of waiting on
+      // one another.  The two blocks are different blocks
+      // of row i, so both are read before either is written.
+      double acc[2][7];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {  // A_ij -= L_ik U_kj, column qc
-        double acc[7];
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 7; ++r) {
-          acc[r] = 0.0;
+        for (int r = 0; r < 7; ++r) acc[h][r] = 0.0;
 #pragma unroll
-          for (int m = 0; m < 7; ++m) acc[r] += lrow[r][m] * G.u[h][m];
-        }
+      for (int m = 0; m < 7; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < 7; ++r) acc[h][r] = __builtin_fma(lrow[r][m], G.u[h][m], acc[h][r]);
+      double av[2][7];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
         const int p = G.pos[h] - 1;
         if (qlane && p >= 0 && p < slice) {
-          double* a = row + p * 49 + qc;
 #pragma unroll
-          for (int r = 0; r < 7; ++r) a[7 * r] -= acc[r];
+          for (int r = 0; r < 7; ++r) av[h][r] = row[p * 49 + qc + 7 * r];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int p = G.pos[h] - 1;
+        if (qlane && p >= 0 && p < slice) {
+#pragma unroll
+          for (int r = 0; r < 7; ++r) row[p * 49 + qc + 7 * r] = av[h][r] - acc[h][r];
         } else if (qlane && p >= slice) {
           const int o = 8 * (p * 49 + qc);
 #pragma unroll
-          for (int r = 0; r < 7; ++r) span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[r]);
+          for (int r = 0; r < 7; ++r) span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[h][r]);
         }
       }
       // a later group may read back what this one stored past the slice
@@ -790,30 +808,58 @@ size_t pc_apply_ws_bytes(const fsi_solver* s) {
 }
 
 // Sweep copy of the factors: FP64 rounded to nearest FP32, or to nearest-even BF16.
-__global__ void __launch_bounds__(256) k_fac_round_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) b[i] = (float)a[i];
+// Rounded factors for the mixed-precision sweeps, written in place over the FP64 factors:
+// rounded value i (w = sizeof(S) bytes) goes to byte w*i of the same buffer.  The values are
+// taken in chunks of kRoundChunk; each workgroup reads its whole chunk into registers before
+// it writes any of it.  Chunk c's output covers FP64 entries [c*B*w/8, (c+1)*B*w/8), so a
+// launch over chunks [a, 8a/w) writes only into chunks below a, all read by earlier launches
+// on the same stream, and reads nothing that it writes.  Chunk 0 (which writes into itself)
+// has a launch of its own.
+constexpr int kRoundChunk = 256 * 8;
+
+__device__ __forceinline__ void round_to(float* out, int64_t i, double x) { out[i] = (float)x; }
+__device__ __forceinline__ void round_to(uint16_t* out, int64_t i, double x) {
+  const uint32_t u = __float_as_uint((float)x);
+  // round to nearest even on the 16 dropped bits; NaN stays NaN
+  const uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
+  out[i] = (uint16_t)(r >> 16);
 }
-__global__ void __launch_bounds__(256) k_fac_round_bf16(int64_t n, const double* __restrict__ a,
-                                                        uint16_t* __restrict__ b) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint32_t u = __float_as_uint((float)a[i]);
-    // round to nearest even on the 16 dropped bits; NaN stays NaN
-    const uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u) : u + 0x7fffu + ((u >> 16) & 1u);
-    b[i] = (uint16_t)(r >> 16);
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_fac_round_inplace(int64_t n, int64_t c0, double* fac) {
+  const int64_t base = (c0 + blockIdx.x) * (int64_t)kRoundChunk;
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t i = base + 256 * u + threadIdx.x;
+    v[u] = i < n ? fac[i] : 0.0;
   }
+  __syncthreads();
+  S* out = reinterpret_cast<S*>(fac);
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int64_t i = base + 256 * u + threadIdx.x;
+    if (i < n) round_to(out, i, v[u]);
+  }
+}
+
+template <typename S>
+static hipError_t round_inplace(fsi_solver* s, int64_t n) {
+  const int64_t nchunk = (n + kRoundChunk - 1) / kRoundChunk;
+  const int64_t ratio = 8 / (int64_t)sizeof(S);
+  hipLaunchKernelGGL(k_fac_round_inplace<S>, dim3(1), dim3(256), 0, s->stream, n, int64_t(0), s->fac);
+  for (int64_t a = 1; a < nchunk;) {
+    const int64_t b = std::min(nchunk, a * ratio);
+    hipLaunchKernelGGL(k_fac_round_inplace<S>, dim3((unsigned)(b - a)), dim3(256), 0, s->stream, n, a, s->fac);
+    a = b;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fac_round(fsi_solver* s) {
   const int64_t n = s->NB * 49;
   if (n == 0 || s->opts.precision == FSI_PREC_FP64) return hipSuccess;
-  if (s->opts.precision == FSI_PREC_FP32)
-    hipLaunchKernelGGL(k_fac_round_f32, dim3(nblk_stride(n)), dim3(256), 0, s->stream, n, s->fac, (float*)s->facs);
-  else
-    hipLaunchKernelGGL(k_fac_round_bf16, dim3(nblk_stride(n)), dim3(256), 0, s->stream, n, s->fac,
-                       (uint16_t*)s->facs);
-  return hipGetLastError();
+  return s->opts.precision == FSI_PREC_FP32 ? round_inplace<float>(s, n) : round_inplace<uint16_t>(s, n);
 }
 
 }  // namespace fsi
