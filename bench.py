@@ -256,6 +256,11 @@ def main():
                 gmres_restart=30,
                 gmres_maxit=600,
                 gmres_rtol=1e-3, newton_rtol=1e-6, newton_maxit=20, precision=args.precision)
+    ref = None
+    if args.precision != 0 and not tube:
+        # the FP64 path first, with its own solver, which is freed before the rounded one is
+        # built (at the largest sizes the two would not fit side by side)
+        ref, ref_sec = fp64_path(fsi, mesh, ph, opts, args.dt, 2 + args.warmup + args.steps, dev, 2 + args.warmup)
     s = fsi.Solver(mesh, ph, opts)
     if args.graphs:
         s.set_graphs(True)
@@ -283,6 +288,8 @@ def main():
     def step(k, mask=None, phase="timed"):
         if tube:
             y_old.copy_(y_start)
+        elif ref is not None:  # every step from the FP64 path's state at the same time
+            y_old.copy_(ref[k])
         s.set_step(dt if tube else (k + 1) * dt, dt, y_old, G[k], None, mask)
         y.copy_(y_old)
         st, rc = s.newton_solve(y, check=False)
@@ -316,7 +323,9 @@ def main():
                 f"unknowns, dt {dt}, {sch}")
 
     try:
-        for k in range(nstart):
+        # with an FP64 reference the start steps are its own: the steps below begin from its
+        # states
+        for k in range(nstart if ref is None else 0):
             st = step(k, rigid, "rigid start")
             log(f"[bench] rigid start step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
         for k in range(nstart, nstart + args.warmup):
@@ -333,7 +342,7 @@ def main():
         s.pc_select(args.sweep_mb)
         tune = {"best_blocks_per_task": args.sweep_mb, "selected": True}
         log(f"[bench] sweep schedule selected: {args.sweep_mb} blocks per task")
-    elif not args.no_tune and nstart + args.warmup > 0:  # sweep schedule timed on the last step's factors,
+    elif not args.no_tune and (nstart if ref is None else 0) + args.warmup > 0:  # sweep schedule timed on the last step's factors,
         # outside the timed steps
         best, us = s.pc_tune(3)
         tune = {"best_blocks_per_task": best, "us_per_apply": {str(k): round(v, 1) for k, v in us.items()}}
@@ -351,11 +360,13 @@ def main():
     # cannot bracket) from one more, eager, step after them
     s.prof_enable(not args.graphs)
     torch.cuda.synchronize()
-    stats = []
+    stats, outs = [], []
     t_start = time.perf_counter()
     try:
         for k in range(nstart + args.warmup, nsteps):
             stats.append(step(k))
+            if ref is not None:
+                outs.append(y.clone())
             log(f"[bench] step {k}: NI {stats[-1]['newton_iters']} LI {stats[-1]['lin_hist'][:stats[-1]['newton_iters']]} "
                 f"cuts {stats[-1]['line_search_cuts']}")
     except StepFailed:
@@ -428,8 +439,15 @@ def main():
     if tube:
         out["roofline"]["note"] = ("the tube's matrix and factors (about 20 MB) stay in the caches: an in-cache "
                                    "rate, not an HBM figure")
-    if args.precision != 0 and not tube:
-        out["error_vs_fp64"] = error_vs_fp64(s, fsi, mesh, ph, opts, G, rigid, dt, nsteps, dev)
+    if ref is not None:
+        rel = [float(torch.linalg.vector_norm(yk - ref[k + 1]) / torch.linalg.vector_norm(ref[k + 1]))
+               for k, yk in zip(range(nstart + args.warmup, nsteps), outs)]
+        out["error_vs_fp64"] = {"per_step_rel_2norm": [float(f"{r:.3e}") for r in rel], "max": float(f"{max(rel):.3e}"),
+                                "newton_rtol": opts["newton_rtol"],
+                                "note": "each timed step starts from the FP64 path's state y_k and is compared with "
+                                        "its y_k+1; both meet the same Newton tolerance"}
+        out["fp64_path"] = {"s_per_step": round(ref_sec, 5), "speedup": round(ref_sec / sec_per_step, 3),
+                            "note": "the plain FP64 path on the same timed steps from the same states"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(counts, args.ilu, mesh.nverts, args.nsub, args.overlap, args.ordering,
                                            small_mesh=mesh if tube else None)
@@ -437,30 +455,33 @@ def main():
     s.close()
 
 
-def error_vs_fp64(s, fsi, mesh, ph, opts, G, rigid, dt, nsteps, dev):
-    """Outside the timed steps: every step of the run taken from the same state (the FP64
-    path's) by the rounded-preconditioner solver s and by an FP64 solver; the relative
-    2-norm difference of their results per step, and the Newton tolerance both meet."""
+def fp64_path(fsi, mesh, ph, opts, dt, nsteps, dev, timed_from):
+    """The FP64 path's states y_0 .. y_nsteps of the run (two rigid-wall steps from rest, then
+    the pulsatile steps), from an FP64 solver that is closed afterwards, and its seconds per
+    step over steps timed_from .. nsteps-1 (the run's timed steps)."""
     import torch
     s64 = fsi.Solver(mesh, ph, dict(opts, precision=0))
-    y_old = torch.zeros(s.n, dtype=torch.float64, device=dev)
-    ya, yb = torch.empty_like(y_old), torch.empty_like(y_old)
-    rel = []
+    rigid = W.rigid_wall_mask(mesh)
+    ys = [torch.zeros(s64.n, dtype=torch.float64, device=dev)]
+    secs = []
     for k in range(nsteps):
-        mask = rigid if k < 2 else None
-        for solver, y in ((s64, ya), (s, yb)):
-            solver.set_step((k + 1) * dt, dt, y_old, G[k], None, mask)
-            y.copy_(y_old)
-            st, rc = solver.newton_solve(y, check=False)
-            if rc != 0:
-                raise RuntimeError(f"comparison step {k} failed with status {rc}")
-        rel.append(float(torch.linalg.vector_norm(yb - ya) / torch.linalg.vector_norm(ya)))
-        y_old.copy_(ya)
-        log(f"[bench] step {k}: rounded-preconditioner state vs FP64 rel {rel[-1]:.3e}")
+        g = torch.as_tensor(W.dirichlet_values(mesh, W.inflow_peak((k + 1) * dt))).to(dev)
+        s64.set_step((k + 1) * dt, dt, ys[-1], g, None, rigid if k < 2 else None)
+        y = ys[-1].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, rc = s64.newton_solve(y, check=False)
+        torch.cuda.synchronize()
+        if k >= timed_from:
+            secs.append(time.perf_counter() - t0)
+        if rc != 0:
+            raise RuntimeError(f"FP64 reference step {k} failed with status {rc}")
+        ys.append(y)
+        log(f"[bench] FP64 reference step {k}: NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]} "
+            f"{time.perf_counter() - t0:.2f}s")
     s64.close()
-    return {"per_step_rel_2norm": [float(f"{r:.3e}") for r in rel], "max": float(f"{max(rel):.3e}"),
-            "newton_rtol": opts["newton_rtol"],
-            "note": "each step from the FP64 path's previous state; both solves meet the same Newton tolerance"}
+    torch.cuda.synchronize()
+    return ys, float(np.mean(secs)) if secs else None
 
 
 if __name__ == "__main__":
