@@ -296,6 +296,190 @@ def run(case="tube", dt=2e-3, train_steps=400, eval_steps=60, amp_eval=18.0, tra
     return summary
 
 
+GUESS_NAMES = ("previous", "extrapolation", "learned")
+
+
+def _summarize(rec, net_f0, picked, l2):
+    out = {"network_F0_rel": float(np.mean(net_f0)) if net_f0 else None, "network_picked": int(picked),
+           "rel_err_upd": {nm: np.mean(v, axis=0).tolist() for nm, v in l2.items() if v}}
+    for name, r in rec.items():
+        out[name] = {"failures": sum(1 for x in r if x["rc"]),
+                     "max_fnorm_over_target": float(max(x["fnorm"] for x in r)),
+                     "NI": float(np.mean([x["NI"] for x in r])),
+                     "LI_per_step": float(np.mean([x["LI"] for x in r])),
+                     "s_per_step": float(np.mean([x["sec"] for x in r])),
+                     "F0_rel": float(np.mean([x["F0"] for x in r]))}
+    return out
+
+
+def run_resumable(case="tree4", state_in=None, state_out="guess_state.npz", budget_s=1000.0, dt=2e-3,
+                  train_steps=400, eval_steps=40, amp_eval=18.0, train_iters=2000, batch=8192, skip=100,
+                  eval_offset=100, groups=("u",), ksub=1024, seed=0, log=print):
+    """The comparison of `run` split over several processes, for meshes whose period of
+    plain steps takes longer than one process may run.  Each call continues from
+    `state_in` (none: from rest), works until about `budget_s` seconds have passed, and
+    writes its state to `state_out` (a NumPy archive without pickled objects):
+
+    - while the trajectory is generated: the plain state y_k in FP64 and, for a seeded set
+      of `ksub` vertices, their states at every step so far, which are the training rows
+      (the network is node-wise, so a vertex subset gives whole training rows);
+    - once it is complete, the network is trained on those rows in the same call, and the
+      evaluation carries y_{n-1} in FP64, y_{n-1} - y_{n-2} in FP32 (the extrapolation's
+      second state is rebuilt from it), the trained parameters and the records so far.
+
+    Returns {"status": "partial", ...} or, after the last evaluation step, the summary of
+    `run` with the plain steps' NI, LI and seconds added."""
+    import torch
+    t_start = time.perf_counter()
+    elapsed = lambda: time.perf_counter() - t_start
+    S = Stepper(case, dt)
+    V = S.mesh.nverts
+    dev = S.s.device
+    st = dict(np.load(state_in, allow_pickle=False)) if state_in else {}
+    if log:
+        log(f"[guess] {case}: V={V}, solver ready after {elapsed():.0f}s; "
+            + (f"resuming phase {int(st['phase'])} at {int(st['k'])}" if st else "starting from rest"))
+
+    def save(**kw):
+        np.savez(state_out, **kw)
+
+    phase = int(st.get("phase", 0))
+    plain = list(map(tuple, st["plain"])) if "plain" in st else []
+    info = json.loads(str(st["info"])) if "info" in st else {}
+    if phase == 0:
+        k = int(st.get("k", 0))
+        y = torch.as_tensor(st["y"]).to(dev) if "y" in st else S.s.vec()
+        sub = st["sub"] if "sub" in st else np.sort(np.random.default_rng(seed).choice(V, ksub, replace=False))
+        isub = torch.as_tensor(sub, device=dev)
+        traj = list(st["traj"]) if "traj" in st else [y.view(-1, 7)[isub].cpu().numpy()]
+        y_prev, per, k0 = None, 0.0, k
+        while k < train_steps:
+            # room for this step and the checkpoint; the last step also needs room for the
+            # training and one evaluation step (about four plain steps)
+            need = 1.5 * per + 30.0 + (120.0 + 4.0 * per if k == train_steps - 1 else 0.0)
+            if k > k0 and elapsed() + need > budget_s:
+                save(phase=0, k=k, y=y.cpu().numpy(), sub=sub, traj=np.array(traj), plain=np.array(plain))
+                return {"status": "partial", "phase": 0, "k": k, "elapsed_s": round(elapsed(), 1)}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.set_step(k, U_AMP, y)
+            yn = y.clone()
+            stt, rc = S.solve(yn)
+            torch.cuda.synchronize()
+            per = time.perf_counter() - t0
+            if rc:
+                raise RuntimeError(f"plain step {k} failed: {rc}")
+            plain.append((stt["newton_iters"], stt["linear_iters"], per))
+            y_prev, y = y, yn
+            traj.append(y.view(-1, 7)[isub].cpu().numpy())
+            k += 1
+            if log and k % 10 == 0:
+                log(f"[guess] plain step {k}: NI {stt['newton_iters']} LI {stt['linear_iters']} {per:.2f}s "
+                    f"(elapsed {elapsed():.0f}s)")
+        # the trajectory is complete: train on the subset's rows
+        tr = [torch.as_tensor(a).to(dev).reshape(-1) for a in traj]
+        samples = [(tr[j - 1], tr[j], tr[j + 1], phase_features((j + 1) * dt, dt, U_AMP))
+                   for j in range(max(4, skip), train_steps)]
+        lg = LearnedGuess(V, batch=batch, seed=seed)
+        lg.fit_scales(samples)
+        fit = [x for i, x in enumerate(samples) if i % 10 != 5]
+        held = [x for i, x in enumerate(samples) if i % 10 == 5]
+        t0 = time.perf_counter()
+        hist = lg.train(fit, steps=train_iters, seed=seed, log=log)
+        gain = lg.fit_gains(held, groups)
+        torch.cuda.synchronize()
+        info = {"train_snapshots": len(fit), "train_rows": len(fit) * len(sub), "subset_vertices": len(sub),
+                "train_s": round(time.perf_counter() - t0, 2), "loss_first": float(np.mean(hist[:10])),
+                "loss_last": float(np.mean(hist[-10:])), "gains_upd": [float(gain[0]), float(gain[3]), float(gain[4])]}
+        if log:
+            log(f"[guess] trained: {info}")
+        params, scales = lg.net.get_params()[0], lg.scales.copy()
+        y1, y2 = y, y_prev
+        j0, evals = -eval_offset, np.zeros((0, 3, 6))
+        net_f0, picked, l2e, l2n = [], 0, [], []
+        del tr, samples, fit, held, traj
+    else:
+        lg = LearnedGuess(V, batch=batch, seed=seed)
+        params, scales = st["params"], st["scales"]
+        lg.net.set_params(params)
+        lg.scales = scales.astype(np.float32)
+        lg.net.set_scales(lg.scales)
+        y1 = torch.as_tensor(st["y"]).to(dev)
+        y2 = y1 - torch.as_tensor(st["dy"]).to(dev).double()
+        j0, evals = int(st["k"]), st["evals"]
+        net_f0, picked = list(st["net_f0"]), int(st["picked"])
+        l2e, l2n = list(st["l2e"]), list(st["l2n"])
+    evals = list(evals)
+    per = 0.0
+    for j in range(j0, eval_steps):
+        if j > j0 and elapsed() + 1.3 * per + 30.0 + (3.0 * per if j == 0 else 0.0) > budget_s:
+            save(phase=1, k=j, y=y1.cpu().numpy(), dy=(y1 - y2).float().cpu().numpy(), params=params, scales=scales,
+                 evals=np.array(evals), net_f0=np.array(net_f0), picked=picked, l2e=np.array(l2e), l2n=np.array(l2n),
+                 plain=np.array(plain), info=np.array(json.dumps(info)))
+            return {"status": "partial", "phase": 1, "k": j, "elapsed_s": round(elapsed(), 1)}
+        te = time.perf_counter()
+        k = train_steps + eval_offset + j
+        t = S.set_step(k, amp_eval, y1)
+        if j < 0:  # plain steps into the next period before the comparison
+            y = y1.clone()
+            stt, rc = S.solve(y)
+            if rc:
+                raise RuntimeError(f"plain step {k} failed: {rc}")
+            y2, y1 = y1, y
+            per = time.perf_counter() - te
+            if log and (j + eval_offset + 1) % 10 == 0:
+                log(f"[guess] plain step {k + 1} (amplitude {amp_eval}): NI {stt['newton_iters']} "
+                    f"LI {stt['linear_iters']} {per:.2f}s (elapsed {elapsed():.0f}s)")
+            continue
+        f_prev = S.fnorm(y1)
+        target = 1e-6 * f_prev
+        row, out = [], {}
+        for name in GUESS_NAMES:
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            if name == "previous":
+                g = y1.clone()
+            elif name == "extrapolation":
+                g = lg.predict(y1, y2)
+            else:
+                ge = lg.predict(y1, y2)
+                gn = lg.predict(y1, y2, phase_features(t, dt, amp_eval))
+                fe, fn = S.fnorm(ge), S.fnorm(gn)
+                net_f0.append(fn / f_prev)
+                g = gn.clone() if fn < fe else ge.clone()
+                picked += fn < fe
+            f0 = S.fnorm(g)
+            stt, rc = S.solve(g, rtol=0.0, atol=target)
+            torch.cuda.synchronize()
+            row.append((rc, stt["newton_iters"], stt["linear_iters"], f0 / f_prev, stt["fnorm"] / target,
+                        time.perf_counter() - tt))
+            out[name] = g
+        evals.append(row)
+        dy = (out["previous"] - y1).view(-1, 7)
+        for lst, gg in ((l2e, ge), (l2n, gn)):
+            e = (gg - out["previous"]).view(-1, 7)
+            lst.append([float(e[:, a:b].norm() / max(float(dy[:, a:b].norm()), 1e-300))
+                        for a, b in ((0, 3), (3, 4), (4, 7))])
+        y2, y1 = y1, out["previous"]
+        per = time.perf_counter() - te
+        if log:
+            log(f"[guess] eval step {j + 1}: " + ", ".join(f"{n} NI {r[1]} LI {r[2]} {r[5]:.2f}s"
+                                                           for n, r in zip(GUESS_NAMES, row))
+                + f" (elapsed {elapsed():.0f}s)")
+    rec = {n: [dict(rc=r[i][0], NI=r[i][1], LI=r[i][2], F0=r[i][3], fnorm=r[i][4], sec=r[i][5]) for r in evals]
+           for i, n in enumerate(GUESS_NAMES)}
+    pl = np.array(plain)
+    summary = {"case": case, "groups": "".join(groups), "vertices": V, "unknowns": S.s.n, "dt": dt,
+               "train_steps": train_steps, "skip": skip, "adam_steps": train_iters, "batch": batch,
+               "eval_steps": eval_steps, "eval_offset": eval_offset, "amp_train": U_AMP, "amp_eval": amp_eval,
+               "plain_period": {"NI": float(pl[:, 0].mean()), "LI_per_step": float(pl[:, 1].mean()),
+                                "s_per_step": float(pl[:, 2].mean())},
+               **info, **_summarize(rec, net_f0, picked, {"extrapolation": l2e, "network": l2n})}
+    S.close()
+    lg.close()
+    return {"status": "done", **summary}
+
+
 def train_bench(batch=8192, steps=200, warmup=20, hidden=128, nlayers=4, seed=0):
     """Adam steps of the guess network on one seeded synthetic batch (FP32 rows of unit
     variance): time per step and the dense-layer FLOP rate it implies."""
@@ -335,9 +519,20 @@ def main():
     ap.add_argument("--eval-offset", type=int, default=0, help="plain steps into the next period before comparing")
     ap.add_argument("--groups", default="u", help="component groups the network corrects, e.g. u or upd")
     ap.add_argument("--train-bench", action="store_true", help="time Adam steps on a synthetic batch only")
+    ap.add_argument("--resumable", action="store_true", help="run in parts that end after --budget seconds")
+    ap.add_argument("--state-in", default=None, help="state written by the previous part")
+    ap.add_argument("--state-out", default="guess_state.npz")
+    ap.add_argument("--budget", type=float, default=1000.0)
     a = ap.parse_args()
     if a.train_bench:
         print(json.dumps(train_bench(batch=a.batch)), flush=True)
+        return
+    if a.resumable:
+        out = run_resumable(case=a.case, state_in=a.state_in, state_out=a.state_out, budget_s=a.budget, dt=a.dt,
+                            train_steps=a.train_steps, eval_steps=a.eval_steps, amp_eval=a.amp_eval,
+                            train_iters=a.train_iters, batch=a.batch, skip=a.skip, eval_offset=a.eval_offset,
+                            groups=tuple(a.groups), log=lambda *x: print(*x, file=sys.stderr, flush=True))
+        print(json.dumps(out), flush=True)
         return
     out = run(case=a.case, dt=a.dt, train_steps=a.train_steps, eval_steps=a.eval_steps, amp_eval=a.amp_eval,
               train_iters=a.train_iters, batch=a.batch, skip=a.skip, eval_offset=a.eval_offset, groups=tuple(a.groups),
