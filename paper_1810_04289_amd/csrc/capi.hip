@@ -561,31 +561,49 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->lslot = upload(s, lbyte);
   }
   {
-    // factorization groups: per pivot, U_k in runs of up to 2*kFacHalf blocks, each with the
-    // forward level of its pivot row
+    // factorization groups: per pivot, the blocks of U_k that have a match in row i (the
+    // others would update nothing), in runs of up to 2*kFacHalf blocks, each with the
+    // forward level of its pivot row.  A block's code is (t << 16) | pos: t its index in U_k,
+    // pos its position in row i plus one; both fit 16 bits since no row reaches 65535 blocks.
+    if (s->max_rowblk >= 65535) {
+      s->err = "a local row of 65535 blocks or more";
+      return FSI_ERR_ARG;
+    }
     std::vector<int32_t> lvl_of(h.lglob.size(), 0);
     for (int sd = 0; sd < h.ns; ++sd)
       for (int L = h.fwd_sub_lvl[sd]; L < h.fwd_sub_lvl[sd + 1]; ++L)
         for (int q = h.fwd_lvl_ptr[L]; q < h.fwd_lvl_ptr[L + 1]; ++q) lvl_of[h.fwd_rows[q]] = L - h.fwd_sub_lvl[sd];
-    std::vector<int32_t> gptr(1, 0), glvl;
+    std::vector<int32_t> gptr(1, 0), glvl, codes, pres;
+    std::vector<int64_t> crow(1, 0);
     std::vector<int4> grp;
     for (size_t i = 0; i + 1 < h.kent_ptr.size(); ++i) {
+      const int64_t ub = h.umap_row[i];
       for (int k = h.kent_ptr[i]; k < h.kent_ptr[i + 1]; ++k) {
         const int pik = h.piv[4 * k], dk = h.piv[4 * k + 1], nu = h.piv[4 * k + 2], mo = h.piv[4 * k + 3];
-        const int run = 2 * kFacHalf;
-        const int ngk = std::max(1, (nu + run - 1) / run);
+        pres.clear();
+        for (int t = 0; t < nu; ++t) {
+          const int32_t pos = h.umap[ub + mo + t];
+          if (pos > 0) pres.push_back((t << 16) | pos);
+        }
+        const int run = 2 * kFacHalf, np = (int)pres.size();
+        const int ngk = std::max(1, (np + run - 1) / run);
         const int plev = lvl_of[h.lcol[h.lrowptr[i] + pik]];
+        const int64_t off = (int64_t)codes.size() - crow.back();  // within row i's codes
         for (int g = 0; g < ngk; ++g) {
-          const int nb = std::min(run, nu - run * g);
-          grp.push_back(make_int4(dk + 1 + run * g, dk, mo + run * g, (pik << 6) | (std::max(nb, 0) << 1) | (g == 0)));
+          const int nb = std::min(run, np - run * g);
+          grp.push_back(make_int4(dk + 1, dk, (int32_t)(off + run * g), (pik << 6) | (std::max(nb, 0) << 1) | (g == 0)));
           glvl.push_back(plev);
         }
+        codes.insert(codes.end(), pres.begin(), pres.end());
       }
       gptr.push_back((int32_t)grp.size());
+      crow.push_back((int64_t)codes.size());
     }
     s->fgrp_ptr = upload(s, gptr);
     s->fgrp = upload(s, grp);
     s->fgrp_lvl = upload(s, glvl);
+    s->umap = upload(s, codes);
+    s->umap_row = upload(s, crow);
     // rows round-robin over the factorization's wavefronts, in level order
     s->fac_nw = fac_layout(s->max_rowblk).waves;
     if (s->fac_nw < 1) {
@@ -614,8 +632,6 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->fw_row = upload(s, wrow);
     s->fw_lvl = upload(s, wlvl);
   }
-  s->umap = upload(s, h.umap);
-  s->umap_row = upload(s, h.umap_row);
   s->sub_row_off = upload(s, h.sub_row_off);
   s->fac = dalloc<double>(s, (size_t)s->NB * 49);
   // rounded factors (FP32 or BF16 sweeps) are written over the FP64 ones after each

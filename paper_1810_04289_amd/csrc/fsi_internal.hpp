@@ -152,8 +152,10 @@ struct fsi_solver {
   int4 *fwd_task_aux = nullptr, *bwd_task_aux = nullptr;
   int32_t* lslot = nullptr;  // per block: LDS byte offset (56 * slot) of its column row's slot
   // factorization groups: row i's are fgrp[fgrp_ptr[i] .. fgrp_ptr[i+1]), for each pivot k
-  // (ascending) U_k in runs of up to 2*kFacHalf blocks (one run if U_k is empty):
-  // {first U block, D_k block, map offset, (position of A_ik << 6) | (blocks << 1) | first run}
+  // (ascending) the blocks of U_k with a match in row i, in runs of up to 2*kFacHalf (one run
+  // if there are none): {first block of U_k, D_k block, offset of the run's codes within row
+  // i's, (position of A_ik << 6) | (blocks << 1) | first run}.  Row i's codes start at
+  // umap[umap_row[i]]; a block's code is (index in U_k << 16) | (position in row i + 1).
   int32_t *fgrp_ptr = nullptr, *umap = nullptr;
   int64_t* umap_row = nullptr;
   int4* fgrp = nullptr;

@@ -20,6 +20,7 @@
 //           forward sweep gathers R_i^delta v on the fly, the backward sweep applies D_i and
 //           writes owned rows straight into z (restricted prolongation).
 #include <algorithm>
+#include <type_traits>
 
 #include "fsi_internal.hpp"
 
@@ -94,29 +95,42 @@ __device__ __forceinline__ FacDesc desc_get(const int4& c, int l) {
                  __builtin_amdgcn_readlane(c.z, l), __builtin_amdgcn_readlane(c.w, l)};
 }
 
+constexpr int kFacCodeLead = 2;  // groups between a group's code loads and its block loads
+
 struct FacGroup {     // what a group reads from memory
   double u[2][7];     // lane q < 63: U_kj[m][q % 7] of the group's blocks q / 7 and 9 + q / 7
   double d;           // lane e < 49: entry e of D_k
-  int pos[2];         // 1 + position of A_ij of those blocks in the row, or 0 (none / beyond U_k)
+  int pos[2];         // 1 + position of A_ij of those blocks in row i, or 0 (no block)
 };
 
-// A group reads up to 18 consecutive blocks of U_k, their map entries and D_k.  The
-// resources end where the group's data end, so missing blocks, padding lanes and groups
-// past the row's end read 0 without touching memory; every group issues the same 17 loads.
-__device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bool real,
-                                               const double* __restrict__ fac, const int32_t* __restrict__ umap,
-                                               int voff_u, int voff_d, int lane) {
+// A group's codes: for lane q, those of its blocks q / 7 and 9 + q / 7, each (t << 16) | pos
+// with t the block's index in U_k and pos its position in row i plus one, or 0 past the
+// group's blocks (the resource ends with them, so those lanes read 0 without touching memory).
+__device__ __forceinline__ void fac_codes_load(int (&c)[2], const FacDesc& F, bool real,
+                                               const int32_t* __restrict__ codes, int lane) {
   const int nblk = real ? (F.flags >> 1) & 31 : 0;
-  const __amdgpu_buffer_rsrc_t ru = span_rsrc(fac + 49 * (size_t)F.ublock, 392 * nblk);
+  const __amdgpu_buffer_rsrc_t rm = span_rsrc(codes + F.moff, 4 * nblk);
 #pragma unroll
   for (int h = 0; h < 2; ++h)
+    c[h] = (int)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (lane / 7) + 4 * kFacHalf * h, 0, 0);
+}
+
+// Its blocks of U_k (at the codes' indices) and D_k.  The blocks' resource runs from U_k's
+// first block to at most 65535 blocks on, and never past the end of the factors.
+__device__ __forceinline__ void fac_blocks_load(FacGroup& G, const int (&c)[2], const FacDesc& F, bool real,
+                                                const double* __restrict__ fac, int64_t nbk, bool qlane, int qc,
+                                                int voff_d) {
+  const int64_t room = real ? nbk - F.ublock : 0;
+  const __amdgpu_buffer_rsrc_t ru =
+      span_rsrc(fac + 49 * (size_t)F.ublock, 392 * (int)(room < 65535 ? room : 65535));
 #pragma unroll
-    for (int m = 0; m < 7; ++m) G.u[h][m] = span_load_f64(ru, voff_u + 392 * kFacHalf * h + 56 * m);
+  for (int h = 0; h < 2; ++h) {
+    const int voff = (qlane && c[h] != 0) ? 8 * (49 * (c[h] >> 16) + qc) : kOutside;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) G.u[h][m] = span_load_f64(ru, voff + 56 * m);
+    G.pos[h] = c[h] & 0xffff;
+  }
   G.d = span_load_f64(span_rsrc(fac + 49 * (size_t)F.dk, real ? 392 : 0), voff_d);
-  const __amdgpu_buffer_rsrc_t rm = span_rsrc(umap + F.moff, 4 * nblk);
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-    G.pos[h] = (int)__builtin_amdgcn_raw_buffer_load_b32(rm, 4 * (lane / 7) + 4 * kFacHalf * h, 0, 0);
 }
 
 // Factorization of one subdomain per workgroup, block IKJ order, one row at a time per
@@ -124,14 +138,16 @@ __device__ __forceinline__ void fac_group_load(FacGroup& G, const FacDesc& F, bo
 // blocks; the blocks of a longer row past the slice stay in global memory and are updated
 // there (read-modify-write by the row's own wavefront, its stores completed before it
 // reads them again), so that a slice need not fit the longest row.
-// Its work is a list of groups built on the host: for each pivot k (ascending), U_k in
-// groups of up to 18 blocks (one group if U_k is empty).  The first group of a pivot forms
+// Its work is a list of groups built on the host: for each pivot k (ascending), the blocks
+// U_kj whose A_ij is in row i's pattern, in groups of up to 18 (one group if there are
+// none); the others would update nothing.  The first group of a pivot forms
 // L_ik = A_ik D_k with lane e < 49 holding entry e, writes it back and reads it into every
 // lane; each group then applies A_ij -= L_ik U_kj to its blocks, lane q < 63 holding column
-// q % 7 of blocks q / 7 and 9 + q / 7 (98 FMAs and 14 LDS read-modify-writes per lane).
-// Each group's blocks are contiguous, so the loads of group t + P - 1 are issued while
-// group t computes, into P rotating register sets; the group descriptors arrive 64 at a
-// time, one per lane, broadcast by readlane.
+// q % 7 of blocks q / 7 and 9 + q / 7 (98 FMAs and 14 LDS read-modify-writes per lane; a
+// group of at most 9 blocks skips the second half).  A group's codes (which blocks, and
+// where in row i) are loaded kFacCodeLead groups before its blocks, and its blocks while
+// group t - P + 1 computes, into P rotating register sets; the group descriptors arrive
+// 64 at a time, one per lane, broadcast by readlane.
 //
 // Schedule.  The rows go to the wavefronts round-robin in level order, and each wavefront
 // works through its rows as far ahead as their pivots allow: a group may start once its
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int4* __restrict__ fgrp,
                                                    const int32_t* __restrict__ fgrp_lvl,
                                                    const int32_t* __restrict__ umap,
-                                                   const int64_t* __restrict__ umap_row,
+                                                   const int64_t* __restrict__ umap_row, int64_t nbk,
                                                    const int32_t* __restrict__ ldiag, double* __restrict__ fac,
                                                    double* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int slice, int wait_limit) {
@@ -171,9 +187,8 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   const int ent = lane < 49 ? lane : 48;  // lanes 49..63 shadow entry 48 and never store
   const bool owner = lane < 49;
   const int rr = ent / 7, cc = ent % 7;
-  const int qb = lane / 7, qc = lane % 7;  // group lanes: block and column
+  const int qc = lane % 7;  // group lanes: column (of blocks lane / 7 and 9 + lane / 7)
   const bool qlane = lane < 7 * kFacHalf;
-  const int voff_u = qlane ? 8 * (49 * qb + qc) : kOutside;
   const int voff_d = owner ? 8 * ent : kOutside;
   double* row = lds + (size_t)wave * (slice * 49 + 56);
   double* dsc = row + (size_t)slice * 49;  // D_k of the current pivot, then L_ik
@@ -222,9 +237,11 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     const int g0 = __builtin_amdgcn_readfirstlane(fgrp_ptr[i]);
     const int ng = __builtin_amdgcn_readfirstlane(fgrp_ptr[i + 1]) - g0;
     // c0 holds groups [cb, cb + 64) (descriptors, and pivot levels in v0) and c1 / v1 the
-    // next chunk; consecutive chunks overlap by P - 1 groups, so group t and group t + P - 1
-    // loaded with it always share c0
-    constexpr int kStride = 64 - (P - 1);
+    // next chunk; consecutive chunks overlap by P - 1 + Q groups, so group t and the groups
+    // t + P - 1 and t + P - 1 + Q loaded with it always share c0
+    constexpr int Q = kFacCodeLead;
+    static_assert(Q >= 1 && Q <= P - 1, "a code slot is reused P groups later");
+    constexpr int kStride = 64 - (P - 1 + Q);
     auto chunk = [&](int t) { return fgrp[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
     auto lchunk = [&](int t) { return fgrp_lvl[ng > 0 ? g0 + (t + lane < ng ? t + lane : ng - 1) : 0]; };
     int cb = 0;
@@ -276,65 +293,77 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       // loops run over m outside so that the fourteen sums interleave instead of waiting on
       // one another.  The two blocks are different blocks
       // of row i, so both are read before either is written.
-      double acc[2][7];
+      auto update = [&](auto nh_c) {
+        constexpr int NH = decltype(nh_c)::value;  // halves with blocks
+        double acc[NH][7];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int r = 0; r < 7; ++r) acc[h][r] = 0.0;
+          for (int r = 0; r < 7; ++r) acc[h][r] = 0.0;
 #pragma unroll
-      for (int m = 0; m < 7; ++m)
+        for (int m = 0; m < 7; ++m)
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+          for (int h = 0; h < NH; ++h)
 #pragma unroll
-          for (int r = 0; r < 7; ++r) acc[h][r] = __builtin_fma(lrow[r][m], G.u[h][m], acc[h][r]);
-      double av[2][7];
+            for (int r = 0; r < 7; ++r) acc[h][r] = __builtin_fma(lrow[r][m], G.u[h][m], acc[h][r]);
+        double av[NH][7];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int p = G.pos[h] - 1;
-        if (qlane && p >= 0 && p < slice) {
+        for (int h = 0; h < NH; ++h) {
+          const int p = G.pos[h] - 1;
+          if (qlane && p >= 0 && p < slice) {
 #pragma unroll
-          for (int r = 0; r < 7; ++r) av[h][r] = row[p * 49 + qc + 7 * r];
+            for (int r = 0; r < 7; ++r) av[h][r] = row[p * 49 + qc + 7 * r];
+          }
         }
-      }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int p = G.pos[h] - 1;
-        if (qlane && p >= 0 && p < slice) {
+        for (int h = 0; h < NH; ++h) {
+          const int p = G.pos[h] - 1;
+          if (qlane && p >= 0 && p < slice) {
 #pragma unroll
-          for (int r = 0; r < 7; ++r) row[p * 49 + qc + 7 * r] = av[h][r] - acc[h][r];
-        } else if (qlane && p >= slice) {
-          const int o = 8 * (p * 49 + qc);
+            for (int r = 0; r < 7; ++r) row[p * 49 + qc + 7 * r] = av[h][r] - acc[h][r];
+          } else if (qlane && p >= slice) {
+            const int o = 8 * (p * 49 + qc);
 #pragma unroll
-          for (int r = 0; r < 7; ++r) span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[h][r]);
+            for (int r = 0; r < 7; ++r)
+              span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[h][r]);
+          }
         }
-      }
+      };
+      if (((F.flags >> 1) & 31) > kFacHalf) update(std::integral_constant<int, 2>());
+      else update(std::integral_constant<int, 1>());
       // a later group may read back what this one stored past the slice
       if (spill) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       wave_lds_sync();
     };
     if (ng > 0) {
+      // step t loads the codes of group t + P - 1 + Q, then the blocks of group t + P - 1
+      // (codes loaded Q steps before), then computes group t; code set g % P is next
+      // written for group g + P, at step g + 1 - Q, after its use at step g - P + 1
       FacGroup buf[P];
+      int cod[P][2];
+      auto step_loads = [&](int gc, int cslot, int gb, int bslot) {
+        const int uc = gc < ng ? gc : ng - 1;
+        fac_codes_load(cod[cslot], desc_get(c0, uc - cb), gc < ng, urow, lane);
+        if (gb >= 0) {
+          const int ubk = gb < ng ? gb : ng - 1;
+          wait_final(__builtin_amdgcn_readlane(v0, ubk - cb));  // pivot row final before its blocks are read
+          fac_blocks_load(buf[bslot], cod[bslot], desc_get(c0, ubk - cb), gb < ng, fac, nbk, qlane, qc, voff_d);
+        }
+      };
 #pragma unroll
-      for (int k = 0; k + 1 < P; ++k) {
-        const int u = k < ng ? k : ng - 1;
-        wait_final(__builtin_amdgcn_readlane(v0, u - cb));  // pivot row final before its blocks are read
-        fac_group_load(buf[k], desc_get(c0, u - cb), k < ng, fac, urow, voff_u, voff_d, lane);
-      }
+      for (int t = -(P - 1 + Q); t < 0; ++t) step_loads(t + P - 1 + Q, (t + P - 1 + Q) % P, t + P - 1, (t + 2 * P - 1) % P);
       for (int t0 = 0; t0 < ng; t0 += P) {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
           const int t = t0 + k;
-          if (t < ng && t + P - 1 - cb == 64) {  // the chunk at cb + kStride starts at group t
+          if (t < ng && t + P - 1 + Q - cb == 64) {  // the chunk at cb + kStride starts at group t
             c0 = c1;
             v0 = v1;
             cb += kStride;
             c1 = chunk(cb + kStride);
             v1 = lchunk(cb + kStride);
           }
-          const int u = t + P - 1 < ng ? t + P - 1 : ng - 1;
-          wait_final(__builtin_amdgcn_readlane(v0, u - cb));
-          fac_group_load(buf[(k + P - 1) % P], desc_get(c0, u - cb), t + P - 1 < ng, fac, urow, voff_u, voff_d,
-                         lane);
+          step_loads(t + P - 1 + Q, (k + P - 1 + Q) % P, t + P - 1, (k + P - 1) % P);
           if (t < ng) consume(buf[k], desc_get(c0, t - cb));
         }
       }
@@ -456,7 +485,7 @@ hipError_t launch_pc_setup(fsi_solver* s) {
     FSI_PROF_LAUNCH(s, "ilu_factor",
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
                                        s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
-                                       s->umap_row,
+                                       s->umap_row, s->NB,
                                        s->ldiag, s->fac, s->udiag, s->flags, fl.slice, s->wait_limit));
     return hipSuccess;
   };

@@ -89,19 +89,70 @@ def short(name: str) -> str:
     return n if len(n) <= 70 else n[:67] + "..."
 
 
+def factor_summary(dirs: list[str], cmds: list[str], copy_mib: int, nblocks: int, out_md: str,
+                   pattern: str = "k_ilu_factor"):
+    """Counters of the factorization kernel, mean per dispatch, from counter runs that each
+    hold some of them (FETCH_SIZE and WRITE_SIZE scaled by the calibration copy), with the
+    shares of wave-cycles spent waiting and issuing VALU and LDS instructions."""
+    vals, scale = {}, {}
+    for d in dirs:
+        with open(_one(d, "*counter_collection.csv")) as f:
+            rows = list(csv.DictReader(f))
+        for c in sorted({r["Counter_Name"] for r in rows}):
+            per = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows if r["Counter_Name"] == c]
+            v = [x for k, x in per if pattern in k]
+            if v:
+                vals[c] = statistics.mean(v)
+            if c in ("FETCH_SIZE", "WRITE_SIZE"):
+                scale[c] = calib_factor(per, copy_mib << 20)
+    L = [f"# Block ILU factorization (`{pattern}`): rocprofv3 counters", "",
+         "Mean per dispatch over the run's factorizations. One counter group per run:", ""]
+    L += [f"    {c}" for c in cmds]
+    L += ["", "| counter | mean per dispatch |", "|---|---:|"]
+    L += [f"| {c} | {v:,.0f} |" for c, v in sorted(vals.items())]
+    wc = vals.get("SQ_WAVE_CYCLES")
+    if wc:
+        L += ["", "| share of wave-cycles | value |", "|---|---:|"]
+        for c in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS"):
+            if c in vals:
+                L.append(f"| {c} | {vals[c] / wc:.3f} |")
+    if "SQ_LDS_BANK_CONFLICT" in vals and "SQ_ACTIVE_INST_LDS" in vals:
+        L += ["", f"LDS bank-conflict cycles per LDS-active cycle: "
+                  f"{vals['SQ_LDS_BANK_CONFLICT'] / max(vals['SQ_ACTIVE_INST_LDS'], 1):.2f}"]
+    if "FETCH_SIZE" in vals and "WRITE_SIZE" in vals:
+        fb = vals["FETCH_SIZE"] * 1024.0 / scale["FETCH_SIZE"]
+        wb = vals["WRITE_SIZE"] * 1024.0 / scale["WRITE_SIZE"]
+        algo = 2.0 * nblocks * 392
+        L += ["", f"HBM bytes per factorization (FETCH_SIZE and WRITE_SIZE scaled by a {copy_mib} MiB copy: "
+                  f"fetch scale {scale['FETCH_SIZE']:.4f}, write scale {scale['WRITE_SIZE']:.4f}): "
+                  f"fetch {fb / 1e9:.2f} GB, write {wb / 1e9:.2f} GB; algorithmic 2 x {nblocks:,} blocks x 392 B "
+                  f"= {algo / 1e9:.2f} GB; ratio {(fb + wb) / algo:.2f}"]
+    src = open(os.path.join(HERE, "csrc", "ilu.hip"), "rb").read()
+    L += ["", f"`ilu.hip` SHA-256: `{hashlib.sha256(src).hexdigest()}`", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(L))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace-dir", required=True)
-    ap.add_argument("--fetch-dir", required=True)
-    ap.add_argument("--write-dir", required=True)
+    ap.add_argument("--factor-dirs", nargs="*", default=None,
+                    help="counter runs of the factorization (then only its summary is written)")
+    ap.add_argument("--factor-cmds", nargs="*", default=None)
+    ap.add_argument("--factor-blocks", type=int, default=0, help="local blocks NB of the run's configuration")
+    ap.add_argument("--trace-dir")
+    ap.add_argument("--fetch-dir")
+    ap.add_argument("--write-dir")
     ap.add_argument("--copy-mib", type=int, required=True)
-    ap.add_argument("--trace-cmd", required=True)
-    ap.add_argument("--fetch-cmd", required=True)
-    ap.add_argument("--write-cmd", required=True)
+    ap.add_argument("--trace-cmd")
+    ap.add_argument("--fetch-cmd")
+    ap.add_argument("--write-cmd")
     ap.add_argument("--algo-bytes", default="", help="JSON of the bench line with the algorithmic bytes")
     ap.add_argument("--out-md", required=True)
-    ap.add_argument("--out-json", required=True)
+    ap.add_argument("--out-json")
     a = ap.parse_args()
+    if a.factor_dirs:
+        factor_summary(a.factor_dirs, a.factor_cmds or [], a.copy_mib, a.factor_blocks, a.out_md)
+        return
 
     nbytes = a.copy_mib << 20
     fv = counter_values(a.fetch_dir, "FETCH_SIZE")
