@@ -160,3 +160,36 @@ def test_uneven_batched_schwarz_ilu0_fp32(fsi_mod):
         assert st["converged"] == 1 and rel <= 1e-3
     for t in gs.values():
         t.close()
+
+
+def bf16_round(x64):
+    """FP64 -> BF16 as the library rounds: to FP32 first, then to nearest even on the 16
+    dropped bits (NaN stays NaN), returned as the FP32 value of the BF16 bits."""
+    u = np.ascontiguousarray(x64, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    nan = (u & 0x7FFFFFFF) > 0x7F800000
+    r = np.where(nan, u | 0x00400000, u + 0x7FFF + ((u >> 16) & 1))
+    return ((r >> 16) << 16).astype(np.uint32).view(np.float32)
+
+
+def test_rounded_factors_in_place(fsi_mod):
+    """The rounded factors are written over the FP64 factors in chunked launches.  On the
+    depth-1 tree (ILU(3), 33 subdomains: 1.3e8 factor entries, about 17 launches for FP32
+    and 9 for BF16) every rounded entry equals the FP64 entry rounded, from the same
+    matrix."""
+    fsi = fsi_mod
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    g = W.dirichlet_values(m, W.inflow_peak(1e-3))
+    o, gs = solvers(fsi, m, dict(nsub=33, overlap=1, ilu_level=3), np.zeros(m.n), g, mask=W.rigid_wall_mask(m))
+    del o
+    f = {}
+    for prec, s in gs.items():
+        y = s.vec()
+        s.impose_dirichlet(y)
+        s.jacobian(y)  # bitwise the same Jacobian in every solver
+        s.pc_setup()
+        pc = s.pc_get()
+        f[prec] = pc["factors"].reshape(-1)
+        s.close()
+    say(f"[rounded factors] {f[0].size} entries")
+    assert np.array_equal(f[fsi.PREC_FP32], f[fsi.PREC_FP64].astype(np.float32).astype(np.float64))
+    assert np.array_equal(f[fsi.PREC_BF16], bf16_round(f[fsi.PREC_FP64]).astype(np.float64))
