@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--validate-cpu-baseline", action="store_true",
                     help="CPU only: time the oracle's phases on the workload's own mesh and compare them with "
                          "the extrapolated depth-1 sample; prints one JSON line")
+    ap.add_argument("--newton-progress", action="store_true",
+                    help="the FP64 reference path reports every Newton iteration as it ends")
     ap.add_argument("--allow-divergence", action="store_true",
                     help="a step that fails ends the run with a JSON line (value null) that records every step's "
                          "Newton and GMRES iterations, instead of an exception")
@@ -260,7 +262,8 @@ def main():
     if args.precision != 0 and not tube:
         # the FP64 path first, with its own solver, which is freed before the rounded one is
         # built (at the largest sizes the two would not fit side by side)
-        ref, ref_sec = fp64_path(fsi, mesh, ph, opts, args.dt, 2 + args.warmup + args.steps, dev, 2 + args.warmup)
+        ref, ref_sec = fp64_path(fsi, mesh, ph, opts, args.dt, 2 + args.warmup + args.steps, dev, 2 + args.warmup,
+                                 reported=args.newton_progress)
     s = fsi.Solver(mesh, ph, opts)
     if args.graphs:
         s.set_graphs(True)
@@ -455,12 +458,39 @@ def main():
     s.close()
 
 
-def fp64_path(fsi, mesh, ph, opts, dt, nsteps, dev, timed_from):
+def newton_reported(s, y, maxit, k):
+    """One step's Newton solve, one library iteration per call (the solver was created with
+    newton_maxit 1), each reported as it ends.  The first call's target, 1e-6 of its
+    ||F_0||, is kept as an absolute one for the later calls, so the iterates are those of a
+    single call; each call evaluates the residual once more at its start."""
+    s.set_newton_tol(1e-6, 0.0)
+    tot = {"newton_iters": 0, "linear_iters": 0, "lin_hist": []}
+    target = None
+    for _ in range(maxit):
+        st, rc = s.newton_solve(y, check=False)
+        if target is None:
+            target = 1e-6 * st["fnorm0"]
+            s.set_newton_tol(0.0, target)
+        ni = st["newton_iters"]
+        tot["newton_iters"] += ni
+        tot["linear_iters"] += st["linear_iters"]
+        tot["lin_hist"] += list(st["lin_hist"][:ni])
+        log(f"[bench] FP64 reference step {k}, Newton iteration {tot['newton_iters']}: ||F|| {st['fnorm']:.3e} "
+            f"(target {target:.3e}), GMRES {list(st['lin_hist'][:ni])}")
+        if st["converged"]:
+            return tot, 0
+        if ni == 0:  # a failure other than the one-iteration limit
+            return tot, rc
+    return tot, 7
+
+
+def fp64_path(fsi, mesh, ph, opts, dt, nsteps, dev, timed_from, reported=False):
     """The FP64 path's states y_0 .. y_nsteps of the run (two rigid-wall steps from rest, then
     the pulsatile steps), from an FP64 solver that is closed afterwards, and its seconds per
-    step over steps timed_from .. nsteps-1 (the run's timed steps)."""
+    step over steps timed_from .. nsteps-1 (the run's timed steps).  reported: every Newton
+    iteration is reported as it ends (for meshes whose start-up steps run for minutes)."""
     import torch
-    s64 = fsi.Solver(mesh, ph, dict(opts, precision=0))
+    s64 = fsi.Solver(mesh, ph, dict(opts, precision=0, newton_maxit=1) if reported else dict(opts, precision=0))
     rigid = W.rigid_wall_mask(mesh)
     ys = [torch.zeros(s64.n, dtype=torch.float64, device=dev)]
     secs = []
@@ -470,7 +500,7 @@ def fp64_path(fsi, mesh, ph, opts, dt, nsteps, dev, timed_from):
         y = ys[-1].clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, rc = s64.newton_solve(y, check=False)
+        st, rc = newton_reported(s64, y, opts["newton_maxit"], k) if reported else s64.newton_solve(y, check=False)
         torch.cuda.synchronize()
         if k >= timed_from:
             secs.append(time.perf_counter() - t0)
