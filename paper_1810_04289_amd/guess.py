@@ -7,9 +7,10 @@ kernels.  Host NumPy only draws the initial weights and fits the 21 feature/outp
 (root mean squares over the training snapshots, read back once); torch holds the pooled
 training rows and shuffles them into mini-batches.
 
-The guess handed to Newton is whichever of the network's guess and the extrapolation has
-the smaller nonlinear residual (two residual evaluations): the residual test of §3 judges
-the network, and the extrapolation is the fallback.
+The guess handed to Newton is whichever of the extrapolation, the network's guess and their
+residual-optimal blend has the smallest nonlinear residual (at most three residual
+evaluations): the residual test of §3 judges the network, and the extrapolation is the
+fallback.
 
 Evaluation at one step n, the same for every guess: Newton runs from the guess, with
 Dirichlet values imposed, until ||F|| <= 1e-6 ||F(y_{n-1})||.  The absolute target is fixed
@@ -148,6 +149,34 @@ class LearnedGuess:
         return self.net.predict(y1, y2, tfeat)
 
 
+def choose_guess(S, ge, gn):
+    """The learned start: of the extrapolation ge, the network's guess gn and their blend
+    ge + a (gn - ge), the one with the smallest residual.  a minimizes the residual's norm
+    along the line through the two residuals, F(ge) + a (F(gn) - F(ge)), clipped to [0, 1];
+    it costs one more residual evaluation.  Returns the guess, the network's residual norm
+    and the a taken (0: extrapolation, 1: network)."""
+    import torch
+    Fe, Fn = S.residual(ge), S.residual(gn)
+    if Fe is None:
+        return gn.clone(), (math.inf if Fn is None else float(Fn.norm())), 1.0
+    fe = float(Fe.norm())
+    if Fn is None:
+        return ge.clone(), math.inf, 0.0
+    fn = float(Fn.norm())
+    D = Fn - Fe
+    dd = float(torch.dot(D, D))
+    a = min(1.0, max(0.0, -float(torch.dot(Fe, D)) / dd)) if dd > 0 else 0.0
+    best, g_best, a_best = fe, ge, 0.0
+    if fn < best:
+        best, g_best, a_best = fn, gn, 1.0
+    if 0.0 < a < 1.0:
+        gb = ge + a * (gn - ge)
+        Fb = S.residual(gb)
+        if Fb is not None and float(Fb.norm()) < best:
+            best, g_best, a_best = float(Fb.norm()), gb, a
+    return g_best.clone(), fn, a_best
+
+
 class Stepper:
     """The plain solver on one case: backward Euler steps with the pulsatile inflow, the
     wall held rigid for the first two steps of a run from rest."""
@@ -179,6 +208,15 @@ class Stepper:
         if self.s.residual(tmp, self.F, check=False):
             return math.inf
         return float(self.F.norm())
+
+    def residual(self, y):
+        """F(y) with the step's Dirichlet values imposed on a copy of y (a new vector), or
+        None where the residual is undefined."""
+        tmp = y.clone()
+        self.s.impose_dirichlet(tmp)
+        if self.s.residual(tmp, self.F, check=False):
+            return None
+        return self.F.clone()
 
     def solve(self, y, rtol=1e-6, atol=0.0):
         self.s.set_newton_tol(rtol, atol)
@@ -227,7 +265,7 @@ def run(case="tube", dt=2e-3, train_steps=400, eval_steps=60, amp_eval=18.0, tra
 
     names = ("previous", "extrapolation", "learned")
     rec = {n: [] for n in names}
-    net_f0, picked, l2 = [], 0, {"extrapolation": [], "network": []}
+    net_f0, picked, alphas, l2 = [], 0, [], {"extrapolation": [], "network": []}
     y1, y2 = ys[-1], ys[-2]
     nfit = len(fit)
     del ys, samples, fit, held
@@ -254,10 +292,10 @@ def run(case="tube", dt=2e-3, train_steps=400, eval_steps=60, amp_eval=18.0, tra
             else:
                 ge = lg.predict(y1, y2)
                 gn = lg.predict(y1, y2, phase_features(t, dt, amp_eval))
-                fe, fn = S.fnorm(ge), S.fnorm(gn)
+                g, fn, a = choose_guess(S, ge, gn)
                 net_f0.append(fn / f_prev)
-                g = gn.clone() if fn < fe else ge.clone()
-                picked += fn < fe
+                alphas.append(a)
+                picked += a > 0.0
             f0 = S.fnorm(g)
             st, rc = S.solve(g, rtol=0.0, atol=target)
             torch.cuda.synchronize()
@@ -283,7 +321,7 @@ def run(case="tube", dt=2e-3, train_steps=400, eval_steps=60, amp_eval=18.0, tra
                "loss_last": float(np.mean(hist[-10:])), "gains_upd": [float(gain[0]), float(gain[3]), float(gain[4])],
                "network_F0_rel": float(np.mean(net_f0)), "eval_offset": eval_offset,
                "rel_err_upd": {nm: np.mean(v, axis=0).tolist() for nm, v in l2.items()},
-               "network_picked": picked}
+               "network_picked": picked, "blend_a_mean": float(np.mean(alphas)) if alphas else None}
     for name, r in rec.items():
         summary[name] = {"failures": sum(1 for x in r if x["rc"]),
                          "max_fnorm_over_target": float(max(x["fnorm"] for x in r)),
@@ -396,7 +434,7 @@ def run_resumable(case="tree4", state_in=None, state_out="guess_state.npz", budg
         params, scales = lg.net.get_params()[0], lg.scales.copy()
         y1, y2 = y, y_prev
         j0, evals = -eval_offset, np.zeros((0, 3, 6))
-        net_f0, picked, l2e, l2n = [], 0, [], []
+        net_f0, picked, alphas, l2e, l2n = [], 0, [], [], []
         del tr, samples, fit, held, traj
     else:
         lg = LearnedGuess(V, batch=batch, seed=seed)
@@ -407,14 +445,15 @@ def run_resumable(case="tree4", state_in=None, state_out="guess_state.npz", budg
         y1 = torch.as_tensor(st["y"]).to(dev)
         y2 = y1 - torch.as_tensor(st["dy"]).to(dev).double()
         j0, evals = int(st["k"]), st["evals"]
-        net_f0, picked = list(st["net_f0"]), int(st["picked"])
+        net_f0, picked, alphas = list(st["net_f0"]), int(st["picked"]), list(st["alphas"])
         l2e, l2n = list(st["l2e"]), list(st["l2n"])
     evals = list(evals)
     per = 0.0
     for j in range(j0, eval_steps):
         if j > j0 and elapsed() + 1.3 * per + 30.0 + (3.0 * per if j == 0 else 0.0) > budget_s:
             save(phase=1, k=j, y=y1.cpu().numpy(), dy=(y1 - y2).float().cpu().numpy(), params=params, scales=scales,
-                 evals=np.array(evals), net_f0=np.array(net_f0), picked=picked, l2e=np.array(l2e), l2n=np.array(l2n),
+                 evals=np.array(evals), net_f0=np.array(net_f0), picked=picked, alphas=np.array(alphas),
+                 l2e=np.array(l2e), l2n=np.array(l2n),
                  plain=np.array(plain), info=np.array(json.dumps(info)))
             return {"status": "partial", "phase": 1, "k": j, "elapsed_s": round(elapsed(), 1)}
         te = time.perf_counter()
@@ -444,10 +483,10 @@ def run_resumable(case="tree4", state_in=None, state_out="guess_state.npz", budg
             else:
                 ge = lg.predict(y1, y2)
                 gn = lg.predict(y1, y2, phase_features(t, dt, amp_eval))
-                fe, fn = S.fnorm(ge), S.fnorm(gn)
+                g, fn, a = choose_guess(S, ge, gn)
                 net_f0.append(fn / f_prev)
-                g = gn.clone() if fn < fe else ge.clone()
-                picked += fn < fe
+                alphas.append(a)
+                picked += a > 0.0
             f0 = S.fnorm(g)
             stt, rc = S.solve(g, rtol=0.0, atol=target)
             torch.cuda.synchronize()
@@ -474,7 +513,8 @@ def run_resumable(case="tree4", state_in=None, state_out="guess_state.npz", budg
                "eval_steps": eval_steps, "eval_offset": eval_offset, "amp_train": U_AMP, "amp_eval": amp_eval,
                "plain_period": {"NI": float(pl[:, 0].mean()), "LI_per_step": float(pl[:, 1].mean()),
                                 "s_per_step": float(pl[:, 2].mean())},
-               **info, **_summarize(rec, net_f0, picked, {"extrapolation": l2e, "network": l2n})}
+               **info, **_summarize(rec, net_f0, picked, {"extrapolation": l2e, "network": l2n}),
+               "blend_a_mean": float(np.mean(alphas)) if alphas else None}
     S.close()
     lg.close()
     return {"status": "done", **summary}
