@@ -836,7 +836,6 @@ size_t pc_apply_ws_bytes(const fsi_solver* s) {
   return (size_t)s->R * 7 * (s->opts.precision == FSI_PREC_FP64 ? sizeof(double) : sizeof(float));
 }
 
-// Sweep copy of the factors: FP64 rounded to nearest FP32, or to nearest-even BF16.
 // Rounded factors for the mixed-precision sweeps, written in place over the FP64 factors:
 // rounded value i (w = sizeof(S) bytes) goes to byte w*i of the same buffer.  The values are
 // taken in chunks of kRoundChunk; each workgroup reads its whole chunk into registers before
