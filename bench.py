@@ -209,7 +209,8 @@ def main():
     ap.add_argument("--ordering", type=int, default=0, help="subdomain ordering: 0 RCM, 1 one-way dissection")
     ap.add_argument("--jac-lag", type=int, default=1, help="Newton iterations per Jacobian and Schwarz setup")
     ap.add_argument("--precision", type=int, default=0,
-                    help="Schwarz sweep precision: 0 FP64, 1 FP32 factors and sweeps, 2 BF16 factors, FP32 sweeps")
+                    help="Schwarz precision: 0 FP64, 1 FP32 sweeps from rounded FP64 factors, 2 BF16 factors "
+                         "with FP32 sweeps, 3 FP32 factorization and sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the row-length rule's sweep schedule")
     ap.add_argument("--sweep-mb", type=int, default=0,
@@ -318,7 +319,8 @@ def main():
     def workload_name():
         sch = (f"{args.nsub} RAS subdomains overlap {args.overlap}, ILU({args.ilu}), {ORDERING[args.ordering]} ordering, "
                f"GMRES(30) rtol 1e-3, Newton rtol 1e-6"
-               + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps"}[args.precision])
+               + {0: "", 1: ", FP32 sweeps", 2: ", BF16 factors with FP32 sweeps",
+                  3: ", FP32 factorization and sweeps"}[args.precision])
         if tube:
             return (f"straight compliant tube, {mesh.nverts} vertices, {mesh.ntets} tets, {s.n} unknowns, one "
                     f"backward-Euler step dt {dt} from the Poiseuille state (peak 30 cm/s), {sch}")
@@ -418,7 +420,8 @@ def main():
         "metric": METRIC, "value": round(sec_per_step, 5), "unit": "s/step", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * sec_per_step, 2), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {0: "f64", 1: "f64 (f32 Schwarz sweeps)", 2: "f64 (bf16 factors, f32 Schwarz sweeps)"}[args.precision],
+        "dtype": {0: "f64", 1: "f64 (f32 Schwarz sweeps)", 2: "f64 (bf16 factors, f32 Schwarz sweeps)",
+                  3: "f64 (f32 Schwarz factorization and sweeps)"}[args.precision],
         "data": "synthetic",
         "config": {"workload": workload_name(),
                    "nverts": mesh.nverts, "ntets": mesh.ntets, "n": s.n, "nnzb": s.nnzb, "nsub": args.nsub,

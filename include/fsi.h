@@ -99,7 +99,11 @@ typedef struct {
  * they take no memory of their own, and run both triangular sweeps in FP32 arithmetic,
  * including accumulation.  The input v and output z of
  * fsi_pc_apply stay FP64, as do residuals, GMRES and the Newton update. */
-enum { FSI_PREC_FP64 = 0, FSI_PREC_FP32 = 1, FSI_PREC_BF16 = 2 };
+/* FSI_PREC_FP32_FACTOR: the factorization itself runs in FP32 (the FP64 Jacobian rounded
+ * to FP32 in the gather, the same operations in the same order as the FP64 factorization),
+ * its factors are stored in FP32 only (half the FP64 memory), and the sweeps are the FP32
+ * ones. */
+enum { FSI_PREC_FP64 = 0, FSI_PREC_FP32 = 1, FSI_PREC_BF16 = 2, FSI_PREC_FP32_FACTOR = 3 };
 
 typedef struct {
   int32_t iters, restarts, converged, pad;
@@ -257,7 +261,8 @@ fsi_status fsi_pc_sizes(const fsi_solver *s, int32_t *nsub, int64_t *nloc_rows,
  * fsi_pc_setup) the factors: strict L blocks (unit diagonal implied), strict U blocks,
  * inverted diagonal blocks in the diagonal positions, and the U diagonal blocks before
  * inversion (udiag).  With FP32 or BF16 sweeps the factors returned are the rounded ones the
- * sweeps use, widened to FP64 (the FP64 factors are overwritten by their rounding). */
+ * sweeps use, widened to FP64 (the FP64 factors are overwritten by their rounding); with an
+ * FP32 factorization, its FP32 factors and udiag, widened. */
 fsi_status fsi_pc_get(const fsi_solver *s, int32_t *part, int32_t *sub_ptr, int32_t *sub_verts,
                       int32_t *sub_nowned, int64_t *blk_ptr, int32_t *lrowptr, int32_t *lcolind,
                       double *factors, double *udiag);

@@ -605,7 +605,7 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->umap = upload(s, codes);
     s->umap_row = upload(s, crow);
     // rows round-robin over the factorization's wavefronts, in level order
-    s->fac_nw = fac_layout(s->max_rowblk).waves;
+    s->fac_nw = fac_layout(s->max_rowblk, s->opts.precision == FSI_PREC_FP32_FACTOR ? 4 : 8).waves;
     if (s->fac_nw < 1) {
       s->err = "a local row is too long to stage in LDS for the factorization";
       return FSI_ERR_ARG;
@@ -633,11 +633,16 @@ fsi_status create_impl(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts*
     s->fw_lvl = upload(s, wlvl);
   }
   s->sub_row_off = upload(s, h.sub_row_off);
-  s->fac = dalloc<double>(s, (size_t)s->NB * 49);
-  // rounded factors (FP32 or BF16 sweeps) are written over the FP64 ones after each
-  // factorization: they share its buffer
-  if (s->opts.precision != FSI_PREC_FP64) s->facs = s->fac;
-  s->udiag = dalloc<double>(s, (size_t)s->R * 49);
+  if (s->opts.precision == FSI_PREC_FP32_FACTOR) {  // the factorization itself in FP32
+    s->fac32 = dalloc<float>(s, (size_t)s->NB * 49);
+    s->udiag32 = dalloc<float>(s, (size_t)s->R * 49);
+  } else {
+    s->fac = dalloc<double>(s, (size_t)s->NB * 49);
+    // rounded factors (FP32 or BF16 sweeps) are written over the FP64 ones after each
+    // factorization: they share its buffer
+    if (s->opts.precision != FSI_PREC_FP64) s->facs = s->fac;
+    s->udiag = dalloc<double>(s, (size_t)s->R * 49);
+  }
   s->ylocal = dalloc<double>(s, (size_t)s->R * 7);
   const int mrs = s->opts.gmres_restart;
   s->Vb = dalloc<double>(s, (size_t)(mrs + 1) * s->n);
@@ -743,7 +748,7 @@ fsi_status fsi_create(const fsi_mesh* m, const fsi_physics* ph, const fsi_opts* 
     return FSI_ERR_ARG;
   if (o->nsub <= 0 || o->nsub > m->nverts || o->overlap < 0 || o->ilu_level < 0 || o->ilu_level > 8 ||
       o->gmres_restart <= 0 || o->gmres_restart > kMaxRestart || o->gmres_maxit <= 0 || (o->ordering != FSI_ORDER_RCM && o->ordering != FSI_ORDER_1WD) ||
-      o->precision < FSI_PREC_FP64 || o->precision > FSI_PREC_BF16 || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
+      o->precision < FSI_PREC_FP64 || o->precision > FSI_PREC_FP32_FACTOR || (int64_t)m->ntets * 16 >= (int64_t)INT32_MAX)
     return FSI_ERR_ARG;
   fsi_solver* s = new (std::nothrow) fsi_solver();
   if (!s) return FSI_ERR_OOM;
@@ -1111,6 +1116,16 @@ fsi_status fsi_pc_get(const fsi_solver* cs, int32_t* part, int32_t* sub_ptr, int
       double** a = (double**)p;
       sync(s);
       const size_t nf = (size_t)s->NB * 49;
+      if (s->opts.precision == FSI_PREC_FP32_FACTOR) {  // FP32 factorization: widened
+        auto widen = [&](double* out, const float* dev, size_t cnt, const char* what) {
+          std::vector<float> tmp(cnt);
+          hip_ok(s, hipMemcpy(tmp.data(), dev, cnt * sizeof(float), hipMemcpyDeviceToHost), what);
+          for (size_t i = 0; i < cnt; ++i) out[i] = (double)tmp[i];
+        };
+        if (a[0]) widen(a[0], s->fac32, nf, "fac");
+        if (a[1]) widen(a[1], s->udiag32, (size_t)s->R * 49, "ud");
+        return FSI_OK;
+      }
       if (a[0] && s->opts.precision == FSI_PREC_FP64) {
         hip_ok(s, hipMemcpy(a[0], s->fac, nf * sizeof(double), hipMemcpyDeviceToHost), "fac");
       } else if (a[0]) {

@@ -170,6 +170,9 @@ struct fsi_solver {
   int32_t* sub_row_off = nullptr;
   double *fac = nullptr, *udiag = nullptr, *ylocal = nullptr;
   void* facs = nullptr;  // FP32 or BF16 factors for the sweeps (precision 1 or 2), in fac's buffer
+  // precision 3: the factorization itself in FP32, into these (fac and udiag stay null)
+  float* fac32 = nullptr;
+  float* udiag32 = nullptr;
   // Krylov / Newton work vectors
   double *Vb = nullptr, *w = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr;
   double *partial = nullptr, *hdev = nullptr, *yvdev = nullptr;
@@ -211,7 +214,7 @@ bool select_plan(fsi_solver* s, int mb);
 struct FacLayout {  // the factorization's wavefronts per subdomain and LDS slice (blocks)
   int waves, slice;
 };
-FacLayout fac_layout(int max_rowblk);
+FacLayout fac_layout(int max_rowblk, int elem_bytes);
 void drop_graphs(fsi_solver* s);
 hipError_t launch_dot_partial(fsi_solver* s, const double* a, const double* b, int64_t n, double* out);
 hipError_t launch_mdot(fsi_solver* s, const double* Vb, int nv, const double* w, int64_t n, double* h);

@@ -35,14 +35,15 @@ static inline unsigned nblk_stride(int64_t n) {
   return (unsigned)(b < (int64_t(1) << 20) ? (b > 0 ? b : 1) : (int64_t(1) << 20));
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) k_ilu_gather(int64_t nb, const int32_t* __restrict__ lsrc,
-                                                    const double* __restrict__ vals, double* __restrict__ fac) {
+                                                    const double* __restrict__ vals, T* __restrict__ fac) {
   const int64_t n = nb * 49, stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < n; gid += stride) {
     const int64_t p = gid / 49;
     const int e = (int)(gid - 49 * p);
     const int src = lsrc[p];
-    fac[gid] = src >= 0 ? vals[49 * (size_t)src + e] : 0.0;
+    fac[gid] = src >= 0 ? (T)vals[49 * (size_t)src + e] : (T)0;
   }
 }
 
@@ -83,6 +84,24 @@ __device__ __forceinline__ void span_store_f64(__amdgpu_buffer_rsrc_t r, int vof
   __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, 0, 0);
 }
 
+// The factorization's arithmetic type: FP64, or FP32 for factors computed in FP32.
+template <typename T>
+__device__ __forceinline__ T span_load_t(__amdgpu_buffer_rsrc_t r, int voff);
+template <>
+__device__ __forceinline__ double span_load_t<double>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return span_load_f64(r, voff);
+}
+template <>
+__device__ __forceinline__ float span_load_t<float>(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+}
+__device__ __forceinline__ void span_store_t(__amdgpu_buffer_rsrc_t r, int voff, double x) { span_store_f64(r, voff, x); }
+__device__ __forceinline__ void span_store_t(__amdgpu_buffer_rsrc_t r, int voff, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, voff, 0, 0);
+}
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 constexpr int kFacDepth = 3;  // factorization groups in flight per wavefront
 constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt operand: vmcnt(0), other counters free
 
@@ -97,9 +116,10 @@ __device__ __forceinline__ FacDesc desc_get(const int4& c, int l) {
 
 constexpr int kFacCodeLead = 2;  // groups between a group's code loads and its block loads
 
+template <typename T>
 struct FacGroup {     // what a group reads from memory
-  double u[2][7];     // lane q < 63: U_kj[m][q % 7] of the group's blocks q / 7 and 9 + q / 7
-  double d;           // lane e < 49: entry e of D_k
+  T u[2][7];          // lane q < 63: U_kj[m][q % 7] of the group's blocks q / 7 and 9 + q / 7
+  T d;                // lane e < 49: entry e of D_k
   int pos[2];         // 1 + position of A_ij of those blocks in row i, or 0 (no block)
 };
 
@@ -117,20 +137,22 @@ __device__ __forceinline__ void fac_codes_load(int (&c)[2], const FacDesc& F, bo
 
 // Its blocks of U_k (at the codes' indices) and D_k.  The blocks' resource runs from U_k's
 // first block to at most 65535 blocks on, and never past the end of the factors.
-__device__ __forceinline__ void fac_blocks_load(FacGroup& G, const int (&c)[2], const FacDesc& F, bool real,
-                                                const double* __restrict__ fac, int64_t nbk, bool qlane, int qc,
+template <typename T>
+__device__ __forceinline__ void fac_blocks_load(FacGroup<T>& G, const int (&c)[2], const FacDesc& F, bool real,
+                                                const T* __restrict__ fac, int64_t nbk, bool qlane, int qc,
                                                 int voff_d) {
+  constexpr int W = (int)sizeof(T);
   const int64_t room = real ? nbk - F.ublock : 0;
   const __amdgpu_buffer_rsrc_t ru =
-      span_rsrc(fac + 49 * (size_t)F.ublock, 392 * (int)(room < 65535 ? room : 65535));
+      span_rsrc(fac + 49 * (size_t)F.ublock, 49 * W * (int)(room < 65535 ? room : 65535));
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int voff = (qlane && c[h] != 0) ? 8 * (49 * (c[h] >> 16) + qc) : kOutside;
+    const int voff = (qlane && c[h] != 0) ? W * (49 * (c[h] >> 16) + qc) : kOutside;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) G.u[h][m] = span_load_f64(ru, voff + 56 * m);
+    for (int m = 0; m < 7; ++m) G.u[h][m] = span_load_t<T>(ru, voff + 7 * W * m);
     G.pos[h] = c[h] & 0xffff;
   }
-  G.d = span_load_f64(span_rsrc(fac + 49 * (size_t)F.dk, real ? 392 : 0), voff_d);
+  G.d = span_load_t<T>(span_rsrc(fac + 49 * (size_t)F.dk, real ? 49 * W : 0), voff_d);
 }
 
 // Factorization of one subdomain per workgroup, block IKJ order, one row at a time per
@@ -159,7 +181,7 @@ __device__ __forceinline__ void fac_blocks_load(FacGroup& G, const int (&c)[2], 
 // level, so it always proceeds: the waits cannot form a cycle.  Each wait is bounded all
 // the same; a wavefront that exceeds the bound raises an error flag and stops waiting, so
 // that the kernel still ends (with its factors marked invalid).
-template <int NT, int P>
+template <int NT, int P, typename T>
 __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ nphase,
                                                    const int32_t* __restrict__ fw_ptr,
                                                    const int32_t* __restrict__ fw_row,
@@ -170,8 +192,8 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
                                                    const int32_t* __restrict__ fgrp_lvl,
                                                    const int32_t* __restrict__ umap,
                                                    const int64_t* __restrict__ umap_row, int64_t nbk,
-                                                   const int32_t* __restrict__ ldiag, double* __restrict__ fac,
-                                                   double* __restrict__ udiag, int32_t* __restrict__ flags,
+                                                   const int32_t* __restrict__ ldiag, T* __restrict__ fac,
+                                                   T* __restrict__ udiag, int32_t* __restrict__ flags,
                                                    int slice, int wait_limit) {
   // Every entry of a block product is a sum over m in ascending order from 0, each term
   // added with one rounding (fused multiply-add), and nothing else is fused or reordered.
@@ -179,7 +201,9 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   // input to about 1e-4 in its factors, so only the same rounded operations give factors
   // that are reproducible anywhere else.
 #pragma clang fp contract(off)
-  extern __shared__ double lds[];
+  extern __shared__ double lds_d[];
+  T* lds = reinterpret_cast<T*>(lds_d);
+  constexpr int W = (int)sizeof(T);
   constexpr int NW = NT / 64;
   const int s = blockIdx.x;
   const int lane = threadIdx.x & 63;
@@ -189,9 +213,9 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
   const int rr = ent / 7, cc = ent % 7;
   const int qc = lane % 7;  // group lanes: column (of blocks lane / 7 and 9 + lane / 7)
   const bool qlane = lane < 7 * kFacHalf;
-  const int voff_d = owner ? 8 * ent : kOutside;
-  double* row = lds + (size_t)wave * (slice * 49 + 56);
-  double* dsc = row + (size_t)slice * 49;  // D_k of the current pivot, then L_ik
+  const int voff_d = owner ? W * ent : kOutside;
+  T* row = lds + (size_t)wave * (slice * 49 + 56);
+  T* dsc = row + (size_t)slice * 49;  // D_k of the current pivot, then L_ik
   const int nL = nphase[s];
   const int wb = fw_ptr[s * NW + wave], we = fw_ptr[s * NW + wave + 1];
   __shared__ int prog[NW];  // progress levels of the wavefronts
@@ -227,9 +251,9 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     const int nbs = nbe < slice * 49 ? nbe : slice * 49;  // entries staged in LDS
     const bool spill = nbe > nbs;                         // blocks past the slice in memory
     const size_t gb = (size_t)rb * 49;
-    double* grow = fac + gb;  // the row in memory
+    T* grow = fac + gb;  // the row in memory
     // the row's blocks past the slice are read and written through buffer instructions
-    const __amdgpu_buffer_rsrc_t rrow = span_rsrc(grow, 8 * nbe);
+    const __amdgpu_buffer_rsrc_t rrow = span_rsrc(grow, W * nbe);
     // this row's part of the U-position map (uniform: kept in scalar registers)
     const int64_t ub = umap_row[i];
     const int32_t* urow = umap + (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ub)) |
@@ -249,7 +273,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     int v0 = lchunk(0), v1 = lchunk(kStride);
     // stage the row: all loads of a round issued before its LDS writes
     for (int e0 = 0; e0 < nbs; e0 += 64 * 8) {
-      double tmp[8];
+      T tmp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
@@ -262,26 +286,26 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       }
     }
     wave_lds_sync();
-    double lrow[7][7];  // L_ik of the current pivot, all entries in every lane
-    auto consume = [&](const FacGroup& G, const FacDesc& F) {
+    T lrow[7][7];  // L_ik of the current pivot, all entries in every lane
+    auto consume = [&](const FacGroup<T>& G, const FacDesc& F) {
       const int pik = F.flags >> 6;
       if (F.flags & 1) {  // first group of the pivot: L_ik = A_ik D_k
         if (owner) dsc[ent] = G.d;
         wave_lds_sync();
-        double l = 0.0;
+        T l = (T)0;
         if (pik < slice) {
 #pragma unroll
-          for (int m = 0; m < 7; ++m) l = __builtin_fma(row[pik * 49 + 7 * rr + m], dsc[7 * m + cc], l);
+          for (int m = 0; m < 7; ++m) l = fma_t(row[pik * 49 + 7 * rr + m], dsc[7 * m + cc], l);
         } else {
 #pragma unroll
           for (int m = 0; m < 7; ++m)
-            l = __builtin_fma(span_load_f64(rrow, 8 * (pik * 49 + 7 * rr + m)), dsc[7 * m + cc], l);
+            l = fma_t(span_load_t<T>(rrow, W * (pik * 49 + 7 * rr + m)), dsc[7 * m + cc], l);
         }
         wave_lds_sync();
         if (owner) {
           dsc[ent] = l;
           if (pik < slice) row[pik * 49 + ent] = l;
-          else span_store_f64(rrow, 8 * (pik * 49 + ent), l);
+          else span_store_t(rrow, W * (pik * 49 + ent), l);
         }
         wave_lds_sync();
 #pragma unroll
@@ -295,18 +319,18 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       // of row i, so both are read before either is written.
       auto update = [&](auto nh_c) {
         constexpr int NH = decltype(nh_c)::value;  // halves with blocks
-        double acc[NH][7];
+        T acc[NH][7];
 #pragma unroll
         for (int h = 0; h < NH; ++h)
 #pragma unroll
-          for (int r = 0; r < 7; ++r) acc[h][r] = 0.0;
+          for (int r = 0; r < 7; ++r) acc[h][r] = (T)0;
 #pragma unroll
         for (int m = 0; m < 7; ++m)
 #pragma unroll
           for (int h = 0; h < NH; ++h)
 #pragma unroll
-            for (int r = 0; r < 7; ++r) acc[h][r] = __builtin_fma(lrow[r][m], G.u[h][m], acc[h][r]);
-        double av[NH][7];
+            for (int r = 0; r < 7; ++r) acc[h][r] = fma_t(lrow[r][m], G.u[h][m], acc[h][r]);
+        T av[NH][7];
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
           const int p = G.pos[h] - 1;
@@ -322,10 +346,10 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
 #pragma unroll
             for (int r = 0; r < 7; ++r) row[p * 49 + qc + 7 * r] = av[h][r] - acc[h][r];
           } else if (qlane && p >= slice) {
-            const int o = 8 * (p * 49 + qc);
+            const int o = W * (p * 49 + qc);
 #pragma unroll
             for (int r = 0; r < 7; ++r)
-              span_store_f64(rrow, o + 56 * r, span_load_f64(rrow, o + 56 * r) - acc[h][r]);
+              span_store_t(rrow, o + 7 * W * r, span_load_t<T>(rrow, o + 7 * W * r) - acc[h][r]);
           }
         }
       };
@@ -339,7 +363,7 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
       // step t loads the codes of group t + P - 1 + Q, then the blocks of group t + P - 1
       // (codes loaded Q steps before), then computes group t; code set g % P is next
       // written for group g + P, at step g + 1 - Q, after its use at step g - P + 1
-      FacGroup buf[P];
+      FacGroup<T> buf[P];
       int cod[P][2];
       auto step_loads = [&](int gc, int cslot, int gb, int bslot) {
         const int uc = gc < ng ? gc : ng - 1;
@@ -374,44 +398,44 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     // exact: the inverse is the same, only its rounding improves (the wall's pivot blocks
     // mix entries from 1e-10 to 1e4).
     const int pdb = __builtin_amdgcn_readfirstlane(ldiag[i]) - rb;  // block position of A_ii
-    double M = pdb < slice ? row[pdb * 49 + ent] : span_load_f64(rrow, 8 * (pdb * 49 + ent));
+    T M = pdb < slice ? row[pdb * 49 + ent] : span_load_t<T>(rrow, W * (pdb * 49 + ent));
     if (owner) udiag[49 * (size_t)i + ent] = M;
     bool bad = false;
-    double rs, cs;  // scale of this lane's row (r_rr) and column (c_cc)
+    T rs, cs;  // scale of this lane's row (r_rr) and column (c_cc)
     {
-      double mx = 0.0;
+      T mx = (T)0;
 #pragma unroll
       for (int m = 0; m < 7; ++m) mx = fmax(mx, fabs(__shfl(M, 7 * rr + m, 64)));
       if (!(mx > 0.0) || !isfinite(mx)) bad = true;
       int e;
       frexp(mx, &e);
-      rs = 1.0 / ldexp(1.0, e - 1);
-      const double Mr = M * rs;
-      mx = 0.0;
+      rs = (T)1 / ldexp((T)1, e - 1);
+      const T Mr = M * rs;
+      mx = (T)0;
 #pragma unroll
       for (int m = 0; m < 7; ++m) mx = fmax(mx, fabs(__shfl(Mr, 7 * m + cc, 64)));
       if (!(mx > 0.0)) bad = true;
       frexp(mx, &e);
-      cs = 1.0 / ldexp(1.0, e - 1);
+      cs = (T)1 / ldexp((T)1, e - 1);
       M = Mr * cs;
     }
-    double Iv = (rr == cc) ? 1.0 : 0.0;
+    T Iv = (rr == cc) ? (T)1 : (T)0;
     for (int p = 0; p < 7; ++p) {
-      double colv[7];
+      T colv[7];
 #pragma unroll
       for (int m = 0; m < 7; ++m) colv[m] = __shfl(M, m * 7 + p, 64);
       int pr = p;
-      double best = fabs(colv[p]);
+      T best = fabs(colv[p]);
       for (int m = p + 1; m < 7; ++m)
         if (fabs(colv[m]) > best) { best = fabs(colv[m]); pr = m; }
       if (!(best > 0.0) || !isfinite(best)) bad = true;
       const int srow = (rr == p) ? pr : (rr == pr ? p : rr);
       M = __shfl(M, srow * 7 + cc, 64);
       Iv = __shfl(Iv, srow * 7 + cc, 64);
-      const double pv = __shfl(M, p * 7 + p, 64);
+      const T pv = __shfl(M, p * 7 + p, 64);
       if (rr == p) { M = M / pv; Iv = Iv / pv; }
-      const double fct = __shfl(M, rr * 7 + p, 64);
-      const double Mp = __shfl(M, p * 7 + cc, 64), Ip = __shfl(Iv, p * 7 + cc, 64);
+      const T fct = __shfl(M, rr * 7 + p, 64);
+      const T Mp = __shfl(M, p * 7 + cc, 64), Ip = __shfl(Iv, p * 7 + cc, 64);
       if (rr != p) { M = M - fct * Mp; Iv = Iv - fct * Ip; }
     }
     // entry (rr, cc) of A^{-1} is c_rr Ah^{-1}(rr, cc) r_cc: c_rr from lane (0, rr), r_cc
@@ -426,12 +450,12 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
     wave_lds_sync();
     if (owner) {
       if (pdb < slice) row[pdb * 49 + ent] = Iv;
-      else span_store_f64(rrow, 8 * (pdb * 49 + ent), Iv);
+      else span_store_t(rrow, W * (pdb * 49 + ent), Iv);
     }
     wave_lds_sync();
     // write back the staged part; blocks past the slice are already in place
     for (int e0 = 0; e0 < nbs; e0 += 64 * 8) {
-      double tmp[8];
+      T tmp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int e = e0 + lane + 64 * u;
@@ -457,27 +481,28 @@ __global__ void __launch_bounds__(NT) k_ilu_factor(const int32_t* __restrict__ n
 // LDS of the factorization: per wavefront a slice of `slice` staged blocks plus D_k, and 64 B
 // for the progress levels.  As many wavefronts (up to four) as slices for the longest row
 // fit; but when four slices of at least 90% of the longest row fit, four wavefronts with
-// such slices, the few longer rows keeping their tails in memory.
-FacLayout fac_layout(int max_rowblk) {
+// such slices, the few longer rows keeping their tails in memory.  elem_bytes: 8 for an
+// FP64 factorization, 4 for FP32.
+FacLayout fac_layout(int max_rowblk, int elem_bytes) {
   const size_t cap = 160 * 1024 - 64;
-  auto per_wave = [](size_t blocks) { return (blocks * 49 + 56) * sizeof(double); };
+  auto per_wave = [&](size_t blocks) { return (blocks * 49 + 56) * (size_t)elem_bytes; };
   const int full = (int)std::min<size_t>(4, cap / per_wave((size_t)max_rowblk));
   if (full >= 4) return FacLayout{4, max_rowblk};
-  const int s4 = (int)((cap / 4 / sizeof(double) - 56) / 49);
+  const int s4 = (int)((cap / 4 / (size_t)elem_bytes - 56) / 49);
   if (10 * s4 >= 9 * max_rowblk) return FacLayout{4, s4};
   return FacLayout{full, max_rowblk};
 }
 
-hipError_t launch_pc_setup(fsi_solver* s) {
-  if (s->NB == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ilu_gather, dim3(nblk_stride(s->NB * 49)), dim3(256), 0, s->stream, s->NB, s->lsrc, s->vals,
-                     s->fac);
+template <typename T>
+static hipError_t pc_setup_t(fsi_solver* s, T* fac, T* udiag) {
+  hipLaunchKernelGGL(k_ilu_gather<T>, dim3(nblk_stride(s->NB * 49)), dim3(256), 0, s->stream, s->NB, s->lsrc,
+                     s->vals, fac);
   // up to four row-staging wavefronts per workgroup, as many as the longest row allows (the
   // rows were dealt to that many wavefronts at create)
-  const FacLayout fl = fac_layout(s->max_rowblk);
+  const FacLayout fl = fac_layout(s->max_rowblk, (int)sizeof(T));
   const int waves = s->fac_nw;
   if (waves < 1 || waves != fl.waves || fl.slice < 1) return hipErrorInvalidConfiguration;
-  const size_t per_wave = ((size_t)fl.slice * 49 + 56) * sizeof(double);
+  const size_t per_wave = ((size_t)fl.slice * 49 + 56) * sizeof(T);
   const size_t lds = per_wave * waves;
   auto go = [&](auto kern, int nt) -> hipError_t {
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -486,14 +511,20 @@ hipError_t launch_pc_setup(fsi_solver* s) {
                     hipLaunchKernelGGL(kern, dim3(s->h.ns), dim3(nt), lds, s->stream, s->fwd_nphase, s->fw_ptr,
                                        s->fw_row, s->fw_lvl, s->lrowptr, s->fgrp_ptr, s->fgrp, s->fgrp_lvl, s->umap,
                                        s->umap_row, s->NB,
-                                       s->ldiag, s->fac, s->udiag, s->flags, fl.slice, s->wait_limit));
+                                       s->ldiag, fac, udiag, s->flags, fl.slice, s->wait_limit));
     return hipSuccess;
   };
   constexpr int P = kFacDepth;
-  hipError_t e = waves >= 4 ? go(k_ilu_factor<256, P>, 256) : waves == 3 ? go(k_ilu_factor<192, P>, 192)
-                 : waves == 2 ? go(k_ilu_factor<128, P>, 128) : go(k_ilu_factor<64, P>, 64);
+  hipError_t e = waves >= 4 ? go(k_ilu_factor<256, P, T>, 256) : waves == 3 ? go(k_ilu_factor<192, P, T>, 192)
+                 : waves == 2 ? go(k_ilu_factor<128, P, T>, 128) : go(k_ilu_factor<64, P, T>, 64);
   if (e != hipSuccess) return e;
   return hipGetLastError();
+}
+
+hipError_t launch_pc_setup(fsi_solver* s) {
+  if (s->NB == 0) return hipSuccess;
+  if (s->opts.precision == FSI_PREC_FP32_FACTOR) return pc_setup_t<float>(s, s->fac32, s->udiag32);
+  return pc_setup_t<double>(s, s->fac, s->udiag);
 }
 
 // Sweeps: one wavefront per row.  Lane = 8*r + c holds entry (r, c) of a 7x7 block
@@ -824,6 +855,7 @@ hipError_t launch_pc_apply_ws(fsi_solver* s, const double* v, double* z, void* y
     case FSI_PREC_FP64: return launch_sweeps_mb<double>(s, s->fac, v, z, yl_ws, flags_ws);
     case FSI_PREC_FP32: return launch_sweeps_mb<float>(s, (const float*)s->facs, v, z, yl_ws, flags_ws);
     case FSI_PREC_BF16: return launch_sweeps_mb<bf16_t>(s, (const bf16_t*)s->facs, v, z, yl_ws, flags_ws);
+    case FSI_PREC_FP32_FACTOR: return launch_sweeps_mb<float>(s, s->fac32, v, z, yl_ws, flags_ws);
     default: return hipErrorInvalidValue;
   }
 }
@@ -886,7 +918,7 @@ static hipError_t round_inplace(fsi_solver* s, int64_t n) {
 
 hipError_t launch_fac_round(fsi_solver* s) {
   const int64_t n = s->NB * 49;
-  if (n == 0 || s->opts.precision == FSI_PREC_FP64) return hipSuccess;
+  if (n == 0 || s->opts.precision == FSI_PREC_FP64 || s->opts.precision == FSI_PREC_FP32_FACTOR) return hipSuccess;
   return s->opts.precision == FSI_PREC_FP32 ? round_inplace<float>(s, n) : round_inplace<uint16_t>(s, n);
 }
 

@@ -83,7 +83,7 @@ _lib = None
 
 
 # precision of the Schwarz triangular sweeps (fsi_opts.precision)
-PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16, PREC_FP32_FACTOR = 0, 1, 2, 3
 
 
 def load_library(path: str = LIB_PATH):

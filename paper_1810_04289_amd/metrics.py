@@ -17,7 +17,7 @@ def sweep_bytes(s, precision: int = 0) -> dict:
              each), the U column slots, the task records, y read, and the owned rows of z
              written (7 doubles per vertex).
     """
-    vb = {0: 8, 1: 4, 2: 2}[precision]
+    vb = {0: 8, 1: 4, 2: 2, 3: 4}[precision]
     yb = 8 if precision == 0 else 4
     pc = s.pc_get(factors=False)
     ns = len(pc["sub_nowned"])

@@ -193,3 +193,58 @@ def test_rounded_factors_in_place(fsi_mod):
     say(f"[rounded factors] {f[0].size} entries")
     assert np.array_equal(f[fsi.PREC_FP32], f[fsi.PREC_FP64].astype(np.float32).astype(np.float64))
     assert np.array_equal(f[fsi.PREC_BF16], bf16_round(f[fsi.PREC_FP64]).astype(np.float64))
+
+
+def test_fp32_factorization(fsi_mod):
+    """The factorization itself in FP32 (precision 3) on the compliant depth-1 tree, ILU(3),
+    subdomains of the benchmark's size.  Its input is the FP64 Jacobian rounded to FP32.
+    Checked: the backward error |LU - A32| / (|L||U|) on sampled rows of several
+    subdomains (A32 that input); GMRES to rtol 1e-3 in the FP64 true residual; and a Newton
+    step from rest to the FP64 tolerance.  The wall's elimination is forward-unstable (a
+    change of one rounding in A moves the factors' leading digits), so FP32 factors differ
+    from the FP64 ones and only the backward error is a property to compare."""
+    import test_gpu_parity as TP
+    fsi = fsi_mod
+    m = W.tree_mesh(depth=1, h=W.TREE_H[1])
+    y0 = np.zeros(m.n)
+    g = W.dirichlet_values(m, 30.0)
+    opts = dict(nsub=33, overlap=1, ilu_level=3, gmres_maxit=600)
+    o = O.Oracle(m, PH, opts)
+    o.set_step(1e-3, 1e-3, y0, g)
+    y = o.impose_dirichlet(W.perturbed_state(m, y0, seed=3))
+    rhs = -o.residual(y)
+    its = {}
+    for prec in (fsi.PREC_FP64, fsi.PREC_FP32_FACTOR):
+        s = fsi.Solver(m, PH, dict(opts, precision=prec))
+        s.set_step(1e-3, 1e-3, s.vec(y0), s.vec(g))
+        s.jacobian(s.vec(y))
+        s.pc_setup()
+        if prec == fsi.PREC_FP32_FACTOR:
+            rp, ci, Vg = s.jacobian_get()
+            V32 = Vg.astype(np.float32).astype(np.float64)
+            pc = s.pc_get()
+            rng = np.random.default_rng(5)
+            worst = max(TP.lu_identity_worst(pc, rp, ci, V32, sub, rng, 12) for sub in (0, 11, 32))
+            say(f"[fp32 factorization, tree1] backward error |LU - A32| / (|L||U|): {worst:.3e}")
+            # an entry of LU is a sum of at most 7 x 107 products (107 blocks in the longest
+            # row), each added with one rounding at u = 2^-24: gamma_n = n u / (1 - n u) =
+            # 4.5e-5 (measured 1.9e-7)
+            assert worst <= 5e-5
+        x = s.vec()
+        st = s.gmres(s.vec(rhs), x)
+        its[prec] = st["iters"]
+        rel = st["rnorm_true"] / st["rnorm0"]
+        say(f"[fp32 factorization, tree1] precision {prec}: GMRES its {st['iters']} true rel {rel:.2e}")
+        assert st["converged"] == 1 and rel <= 1e-3
+        if prec == fsi.PREC_FP32_FACTOR:
+            mask = W.rigid_wall_mask(m)
+            s.set_step(1e-3, 1e-3, s.vec(y0), s.vec(g), None, mask)
+            o.set_step(1e-3, 1e-3, y0, g, extra_mask=mask)
+            yd = s.vec(y0)
+            st, rc = s.newton_solve(yd)
+            say(f"[fp32 factorization newton, tree1] rc {rc} NI {st['newton_iters']} LI {st['lin_hist'][:st['newton_iters']]}")
+            assert rc == 0 and st["converged"] == 1
+            F = o.residual(yd.cpu().numpy())
+            assert np.linalg.norm(F) <= 1.01e-6 * st["fnorm0"]
+        s.close()
+    assert its[fsi.PREC_FP32_FACTOR] <= 2 * its[fsi.PREC_FP64] + 10
