@@ -6,6 +6,7 @@
 #include <atomic>
 #include <climits>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -18,8 +19,13 @@
 namespace fsi {
 
 // Host threads of the set-up: every threaded step computes per-item results that do not
-// depend on the thread count, so the products are the same for any count.
+// depend on the thread count, so the products are the same for any count.  The count is the
+// hardware's, at most 16, unless FSI_SETUP_THREADS (1 to 64) sets it.
 static int setup_threads() {
+  if (const char* e = std::getenv("FSI_SETUP_THREADS")) {
+    const int t = std::atoi(e);
+    if (t >= 1 && t <= 64) return t;
+  }
   const unsigned hw = std::thread::hardware_concurrency();
   return (int)std::max(1u, std::min(hw, 16u));
 }
