@@ -82,7 +82,8 @@ def _todict(st) -> dict:
 _lib = None
 
 
-# precision of the Schwarz triangular sweeps (fsi_opts.precision)
+# precision of the Schwarz preconditioner (fsi_opts.precision): FP64; FP32 sweeps from rounded
+# FP64 factors; BF16 factors with FP32 sweeps; FP32 factorization and sweeps
 PREC_FP64, PREC_FP32, PREC_BF16, PREC_FP32_FACTOR = 0, 1, 2, 3
 
 
